@@ -23,6 +23,9 @@ from dataclasses import dataclass
 
 import numpy as np
 
+# bump whenever a recipe below changes: stored expected values record it
+GEN_VERSION = 1
+
 MASK64 = (1 << 64) - 1
 GOLDEN_GAMMA = 0x9E3779B97F4A7C15
 

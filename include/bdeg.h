@@ -1,0 +1,184 @@
+/*
+ * bdeg -- exact degree of the C*-solution set of a binomial system x^A = b
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section 2 of Chen & Mehta, "Parallel degree computation for
+ * solution space of binomial systems"): a system of m binomial equations
+ * c1 x^alpha + c2 x^beta = 0 in n variables is x^A = b with A the integer
+ * exponent matrix.  HERE A IS m x n, ROW-MAJOR, ONE ROW PER BINOMIAL
+ * (row i = alpha^(i) - beta^(i)); the paper writes the transpose.
+ *
+ * For a consistent system the library returns, exactly:
+ *   k          = n - rank(A), the dimension of every component;
+ *   components = |d_1 ... d_r|, the product of the nonzero Smith invariant
+ *                factors (Proposition "topological"): the number of components;
+ *   nvol       = k! Vol_k(conv{0, v_1, ..., v_n}) where v_i is row i of a
+ *                saturated integer basis V (n x k) of ker(A): the degree of
+ *                each component (Proposition "degree", eq. "deg-vol").
+ * The degree of the whole solution set is components * nvol.
+ *
+ * nvol is computed on the GPU as the sum of |det| over the lower facets of a
+ * generic integer lifting of the points (Section 4, eqs. "lower-face" and
+ * "simplex-vol"): every candidate (k+1)-subset is decided exactly in integer
+ * arithmetic.  A lifting that produces a non-simplicial lower face (a "tie")
+ * is redrawn; the result never depends on the seed, only `attempts` does.
+ *
+ * Conventions shared by every entry point
+ *   - All pointers are HOST pointers unless stated; the caller owns every
+ *     buffer, the library copies inputs and keeps no caller pointer.
+ *   - Integers are little-endian; 128-bit results are {lo, hi} words.
+ *   - Return value: BDEG_OK (0) or a negative BDEG_E_* code; bdeg_strerror
+ *     gives a message.  On error the outputs are left in an unspecified state
+ *     unless stated.
+ *   - Thread safety: calls may come from several host threads; the library
+ *     serialises device work on its own stream per process.
+ *   - The device is the process's current HIP device at the first call
+ *     (or the one given to bdeg_init).  No GPU => BDEG_E_DEVICE.
+ */
+#ifndef BDEG_H
+#define BDEG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BDEG_OK 0
+#define BDEG_PENDING 1        /* serving: the request is not finished yet */
+#define BDEG_E_ARG (-1)       /* null pointer, bad size, bad lifting width */
+#define BDEG_E_OVERFLOW (-2)  /* host int64 algebra overflowed, or the point set's minor bounds
+                                 exceed what the exact device arithmetic certifies */
+#define BDEG_E_TOO_LARGE (-3) /* k > BDEG_MAX_K, or more than 2^63 candidates */
+#define BDEG_E_TIE (-4)       /* no generic lifting found in BDEG_MAX_ATTEMPTS draws */
+#define BDEG_E_DEVICE (-5)    /* HIP runtime error or no device */
+#define BDEG_E_NOMEM (-6)     /* device or host allocation failed / over budget */
+#define BDEG_E_STATE (-7)     /* unknown ticket, closed server, or result already taken */
+
+#define BDEG_F_NEEDS_CONSISTENCY 1u /* rank < m: the set is empty unless b^(Q_0) = 1
+                                       (Section 2, eq. "consistency"); b is not an input */
+
+#define BDEG_MAX_N 63        /* variables: N = n + 1 points fit one 64-lane wavefront */
+#define BDEG_MAX_K 12        /* kernel dimension handled on the device */
+#define BDEG_MAX_ATTEMPTS 16 /* lifting draws before BDEG_E_TIE */
+
+typedef struct {
+  uint64_t lo, hi;
+} bdeg_u128;
+
+typedef struct {
+  int32_t status;       /* BDEG_OK or a BDEG_E_* code for this system */
+  int32_t k;            /* n - rank(A) */
+  int32_t rank;         /* r */
+  int32_t attempts;     /* lifting draws used (1 + tie retries); 0 when k == 0 */
+  uint32_t flags;       /* BDEG_F_* */
+  uint32_t reserved;
+  bdeg_u128 components; /* |prod of nonzero Smith invariant factors| */
+  bdeg_u128 nvol;       /* k! Vol_k(conv{0, v_1..v_n}); 1 when k == 0 */
+  uint64_t candidates;  /* C(n+1, k+1): candidate simplices decided */
+  uint64_t cells;       /* lower facets of the final lifting (cells of the subdivision) */
+} bdeg_result;
+
+/* Device work counters of the last device run (for roofline accounting). */
+typedef struct {
+  uint64_t nodes[BDEG_MAX_K]; /* nodes[t]: subtree nodes created at depth t (t+1 points fixed),
+                                 1 <= t <= k-1; nodes[k-1] are the ridges (k points fixed) */
+  uint64_t pruned;            /* prefixes cut because the new point is affinely dependent */
+  uint64_t leaves;            /* candidates tested with a nonzero determinant */
+  uint64_t tiles;             /* work units processed */
+  float kernel_ms;            /* device time of the enumeration kernel, HIP events */
+  float total_ms;             /* device time of the whole device pass (clear, lift, enumerate) */
+} bdeg_stats;
+
+/* Optional: select the HIP device (default: current device at first use).
+ * Must precede every other call; BDEG_E_STATE if the library is already set up. */
+int bdeg_init(int32_t device);
+
+/*
+ * Degree data of one binomial system (Sections 2-4).
+ *   A          m x n row-major int64 exponent matrix, 1 <= m, 1 <= n <= BDEG_MAX_N.
+ *   seed       selects the lifting stream (results do not depend on it).
+ *   lift_bits  heights uniform in [0, 2^lift_bits), 2 <= lift_bits <= 30.
+ *   out        filled on BDEG_OK; out->status repeats the return code.
+ */
+int bdeg_degree(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int32_t lift_bits,
+                bdeg_result *out);
+
+/*
+ * Many systems in one device launch (continuous tile queue over all systems).
+ *   A_concat   the matrices back to back, system s is m[s] x n[s] row-major.
+ *   m, n       count entries each.  out: count results (per-system status).
+ * Returns BDEG_OK if every system succeeded, else the first failing code
+ * (every out[s].status is still filled).
+ */
+int bdeg_degree_batch(const int64_t *A_concat, const int32_t *m, const int32_t *n, int32_t count,
+                      uint64_t seed, int32_t lift_bits, bdeg_result *out);
+
+/*
+ * Prepared batch: host algebra done once, point sets and work lists resident
+ * in device memory, device path captured as a HIP graph and replayable.
+ *   bdeg_batch_create   host prologue (Smith form, kernel points, bounds,
+ *                       tiling) + upload; *out owns device memory.
+ *   bdeg_batch_run      enqueue one full device pass (clear accumulators,
+ *                       lifting, enumeration) on the library stream; async.
+ *   bdeg_batch_results  wait, redraw liftings of tied systems (uncaptured
+ *                       reruns) until none ties, fill out[count].
+ *   bdeg_batch_stats    counters and HIP-event times of the last run.
+ *   bdeg_batch_destroy  free everything.
+ */
+typedef struct bdeg_batch bdeg_batch;
+int bdeg_batch_create(const int64_t *A_concat, const int32_t *m, const int32_t *n, int32_t count,
+                      uint64_t seed, int32_t lift_bits, bdeg_batch **out);
+int bdeg_batch_run(bdeg_batch *b);
+int bdeg_batch_results(bdeg_batch *b, bdeg_result *out);
+int bdeg_batch_stats(const bdeg_batch *b, bdeg_stats *out);
+int bdeg_batch_destroy(bdeg_batch *b);
+
+/*
+ * Volume of a caller's point set with caller's heights, restricted to the
+ * candidates whose colex rank lies in [rank_lo, rank_hi)
+ * (rank {c_0 < ... < c_k} = sum_i C(c_i, i+1); pass rank_hi = UINT64_MAX for
+ * all).  No tie retry: *tie reports a non-generic lower face in the range.
+ *   points   N x k row-major int32 (N <= 64, 1 <= k <= BDEG_MAX_K);
+ *   heights  N int64, |h| < 2^40.
+ * The point set must satisfy the device bound (see BDEG_E_OVERFLOW).
+ */
+int bdeg_nvol_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k,
+                     uint64_t rank_lo, uint64_t rank_hi, bdeg_u128 *nvol, int32_t *tie,
+                     uint64_t *cells);
+
+/*
+ * Host prologue only (no device): rank, k, components and the point set
+ * {0, v_1..v_n} the device would use (Euclid column elimination with a
+ * pairwise-reduced saturated kernel basis).  points must hold (n+1)*n int32;
+ * the first (n+1)*k are written, point 0 first.
+ */
+int bdeg_kernel_points(const int64_t *A, int32_t m, int32_t n, int32_t *k, int32_t *rank,
+                       bdeg_u128 *components, int32_t *points);
+
+/*
+ * Serving: requests are admitted into device-resident slots as device memory
+ * (budget bytes) allows, their work joins a shared device tile queue that is
+ * drained in bounded steps, so requests overlap on the device; each result
+ * is identical to the one bdeg_degree gives for the same input.
+ *   bdeg_serve_open    start the engine (a host thread owns the device work).
+ *   bdeg_serve_submit  copy A, queue the request, return a ticket (non-blocking).
+ *   bdeg_serve_poll    BDEG_OK with *out filled (once), or BDEG_PENDING.
+ *   bdeg_serve_wait    block until done, then as poll.
+ *   bdeg_serve_close   finish queued work, stop the engine, free everything.
+ */
+typedef struct bdeg_server bdeg_server;
+int bdeg_serve_open(size_t device_mem_budget, bdeg_server **out);
+int bdeg_serve_submit(bdeg_server *s, const int64_t *A, int32_t m, int32_t n, uint64_t seed,
+                      int32_t lift_bits, uint64_t *ticket);
+int bdeg_serve_poll(bdeg_server *s, uint64_t ticket, bdeg_result *out);
+int bdeg_serve_wait(bdeg_server *s, uint64_t ticket, bdeg_result *out);
+int bdeg_serve_close(bdeg_server *s);
+
+const char *bdeg_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDEG_H */

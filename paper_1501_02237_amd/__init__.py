@@ -1,0 +1,267 @@
+"""Python binding of libbdeg (include/bdeg.h): argument marshalling only.
+
+Every step of the degree path runs inside the C-ABI library (host algebra in
+C++, enumeration in HIP kernels on the GPU).  There is no Python or CPU
+fallback: if the library is missing, importing the functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbdeg.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "bdeg.h")
+
+BDEG_OK = 0
+BDEG_PENDING = 1
+BDEG_E_ARG = -1
+BDEG_E_OVERFLOW = -2
+BDEG_E_TOO_LARGE = -3
+BDEG_E_TIE = -4
+BDEG_E_DEVICE = -5
+BDEG_E_NOMEM = -6
+BDEG_E_STATE = -7
+BDEG_F_NEEDS_CONSISTENCY = 1
+MAX_N = 63
+MAX_K = 12
+U64_MAX = (1 << 64) - 1
+
+
+class BdegError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})" if what else f"{strerror(code)} ({code})")
+
+
+class U128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+    @property
+    def value(self) -> int:
+        return (self.hi << 64) | self.lo
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("k", ctypes.c_int32), ("rank", ctypes.c_int32), ("attempts", ctypes.c_int32),
+        ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("components", U128), ("nvol", U128),
+        ("candidates", ctypes.c_uint64), ("cells", ctypes.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return dict(status=self.status, k=self.k, rank=self.rank, attempts=self.attempts, flags=self.flags,
+                    comps=self.components.value, nvol=self.nvol.value, candidates=self.candidates, cells=self.cells)
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("nodes", ctypes.c_uint64 * MAX_K), ("pruned", ctypes.c_uint64), ("leaves", ctypes.c_uint64),
+        ("tiles", ctypes.c_uint64), ("kernel_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "nodes"}
+        d["nodes"] = list(self.nodes)
+        return d
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libbdeg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1501_02237_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+    sig = {
+        "bdeg_init": ([I32], ctypes.c_int),
+        "bdeg_degree": ([P, I32, I32, U64, I32, P], ctypes.c_int),
+        "bdeg_degree_batch": ([P, P, P, I32, U64, I32, P], ctypes.c_int),
+        "bdeg_batch_create": ([P, P, P, I32, U64, I32, P], ctypes.c_int),
+        "bdeg_batch_run": ([P], ctypes.c_int),
+        "bdeg_batch_results": ([P, P], ctypes.c_int),
+        "bdeg_batch_stats": ([P, P], ctypes.c_int),
+        "bdeg_batch_destroy": ([P], ctypes.c_int),
+        "bdeg_nvol_points": ([P, P, I32, I32, U64, U64, P, P, P], ctypes.c_int),
+        "bdeg_kernel_points": ([P, I32, I32, P, P, P, P], ctypes.c_int),
+        "bdeg_serve_open": ([SZ, P], ctypes.c_int),
+        "bdeg_serve_submit": ([P, P, I32, I32, U64, I32, P], ctypes.c_int),
+        "bdeg_serve_poll": ([P, U64, P], ctypes.c_int),
+        "bdeg_serve_wait": ([P, U64, P], ctypes.c_int),
+        "bdeg_serve_close": ([P], ctypes.c_int),
+        "bdeg_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _ = I64
+    _lib = L
+    return L
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/bdeg.h."""
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(bdeg_\w+)\s*\(", src, flags=re.M)))
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().bdeg_strerror(code).decode()
+    except ImportError:
+        return f"error {code}"
+
+
+def _mat(A) -> np.ndarray:
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.int64))
+    if A.ndim != 2:
+        raise ValueError("A must be a 2-D integer matrix (m x n)")
+    return A
+
+
+def degree(A, seed: int = 1, lift_bits: int = 20, check: bool = True) -> dict:
+    """{status, k, rank, comps, nvol, attempts, flags, candidates, cells} of x^A = b."""
+    A = _mat(A)
+    r = Result()
+    rc = lib().bdeg_degree(A.ctypes.data, A.shape[0], A.shape[1], seed & U64_MAX, lift_bits, ctypes.byref(r))
+    if check and rc != BDEG_OK:
+        raise BdegError(rc, "bdeg_degree")
+    d = r.as_dict()
+    d["status"] = rc if rc != BDEG_OK else d["status"]
+    return d
+
+
+def _pack(mats):
+    mats = [_mat(A) for A in mats]
+    m = np.array([A.shape[0] for A in mats], dtype=np.int32)
+    n = np.array([A.shape[1] for A in mats], dtype=np.int32)
+    cat = np.ascontiguousarray(np.concatenate([A.ravel() for A in mats]).astype(np.int64))
+    return cat, m, n
+
+
+def degree_batch(mats, seed: int = 1, lift_bits: int = 20) -> list[dict]:
+    cat, m, n = _pack(mats)
+    out = (Result * len(m))()
+    lib().bdeg_degree_batch(cat.ctypes.data, m.ctypes.data, n.ctypes.data, len(m), seed & U64_MAX, lift_bits, out)
+    return [r.as_dict() for r in out]
+
+
+def kernel_points(A) -> tuple[int, int, int, np.ndarray]:
+    """Host prologue only: (k, rank, comps, points (n+1) x k int32)."""
+    A = _mat(A)
+    m, n = A.shape
+    k, rank, comps = ctypes.c_int32(), ctypes.c_int32(), U128()
+    pts = np.zeros((n + 1) * max(n, 1), dtype=np.int32)
+    rc = lib().bdeg_kernel_points(A.ctypes.data, m, n, ctypes.byref(k), ctypes.byref(rank), ctypes.byref(comps),
+                                  pts.ctypes.data)
+    if rc != BDEG_OK:
+        raise BdegError(rc, "bdeg_kernel_points")
+    return k.value, rank.value, comps.value, pts[: (n + 1) * k.value].reshape(n + 1, k.value)
+
+
+@dataclass
+class VolumeRange:
+    nvol: int
+    tie: bool
+    cells: int
+
+
+def nvol_points(points, heights, rank_lo: int = 0, rank_hi: int | None = None) -> VolumeRange:
+    P = np.ascontiguousarray(np.asarray(points, dtype=np.int32))
+    H = np.ascontiguousarray(np.asarray(heights, dtype=np.int64))
+    N, k = P.shape
+    nv, tie, cells = U128(), ctypes.c_int32(), ctypes.c_uint64()
+    rc = lib().bdeg_nvol_points(P.ctypes.data, H.ctypes.data, N, k, rank_lo, U64_MAX if rank_hi is None else rank_hi,
+                                ctypes.byref(nv), ctypes.byref(tie), ctypes.byref(cells))
+    if rc != BDEG_OK:
+        raise BdegError(rc, "bdeg_nvol_points")
+    return VolumeRange(nv.value, bool(tie.value), cells.value)
+
+
+class Batch:
+    """Prepared, device-resident batch with a captured device pass."""
+
+    def __init__(self, mats, seed: int = 1, lift_bits: int = 20):
+        cat, m, n = _pack(mats)
+        self.count = len(m)
+        self._h = ctypes.c_void_p()
+        rc = lib().bdeg_batch_create(cat.ctypes.data, m.ctypes.data, n.ctypes.data, self.count, seed & U64_MAX,
+                                     lift_bits, ctypes.byref(self._h))
+        if rc != BDEG_OK:
+            raise BdegError(rc, "bdeg_batch_create")
+
+    def run(self) -> None:
+        rc = lib().bdeg_batch_run(self._h)
+        if rc != BDEG_OK:
+            raise BdegError(rc, "bdeg_batch_run")
+
+    def results(self) -> list[dict]:
+        out = (Result * self.count)()
+        lib().bdeg_batch_results(self._h, out)
+        return [r.as_dict() for r in out]
+
+    def stats(self) -> dict:
+        s = Stats()
+        lib().bdeg_batch_stats(self._h, ctypes.byref(s))
+        return s.as_dict()
+
+    def close(self) -> None:
+        if self._h:
+            lib().bdeg_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request engine (bdeg_serve_*)."""
+
+    def __init__(self, device_mem_budget: int = 256 << 20):
+        self._h = ctypes.c_void_p()
+        rc = lib().bdeg_serve_open(device_mem_budget, ctypes.byref(self._h))
+        if rc != BDEG_OK:
+            raise BdegError(rc, "bdeg_serve_open")
+
+    def submit(self, A, seed: int = 1, lift_bits: int = 20) -> int:
+        A = _mat(A)
+        t = ctypes.c_uint64()
+        rc = lib().bdeg_serve_submit(self._h, A.ctypes.data, A.shape[0], A.shape[1], seed & U64_MAX, lift_bits,
+                                     ctypes.byref(t))
+        if rc != BDEG_OK:
+            raise BdegError(rc, "bdeg_serve_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        r = Result()
+        rc = lib().bdeg_serve_poll(self._h, ticket, ctypes.byref(r))
+        if rc == BDEG_PENDING:
+            return None
+        if rc != BDEG_OK and rc != r.status:
+            raise BdegError(rc, "bdeg_serve_poll")
+        return r.as_dict()
+
+    def wait(self, ticket: int) -> dict:
+        r = Result()
+        rc = lib().bdeg_serve_wait(self._h, ticket, ctypes.byref(r))
+        if rc != BDEG_OK and rc != r.status:
+            raise BdegError(rc, "bdeg_serve_wait")
+        return r.as_dict()
+
+    def close(self) -> None:
+        if self._h:
+            lib().bdeg_serve_close(self._h)
+            self._h = ctypes.c_void_p()

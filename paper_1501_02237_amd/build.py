@@ -1,0 +1,57 @@
+"""Build libbdeg.so (the C-ABI library) in-tree with hipcc for gfx950.
+
+    python -m paper_1501_02237_amd.build
+
+Every source is compiled by hipcc; kernels are compiled for gfx950 only with
+packed-FP32 instruction selection disabled."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libbdeg.so")
+BUILD = os.path.join(ROOT, "_build")
+SOURCES = ["algebra.cpp", "tiles.cpp", "runtime.cpp", "api.cpp", "serve.cpp", "kernels.hip"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+
+def _flags(src: str) -> list[str]:
+    f = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]
+    f += [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    if not src.endswith(".hip"):
+        f += ["-x", "hip"] if False else []
+    return f
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    objs, procs = [], []
+    t0 = time.time()
+    for s in SOURCES:
+        src = os.path.join(CSRC, s)
+        obj = os.path.join(BUILD, s + ".o")
+        cmd = [HIPCC, *_flags(s), "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((s, subprocess.Popen(cmd)))
+        objs.append(obj)
+    bad = [s for s, p in procs if p.wait() != 0]
+    if bad:
+        raise RuntimeError(f"hipcc failed on {bad}")
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB} in {time.time() - t0:.1f}s", flush=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

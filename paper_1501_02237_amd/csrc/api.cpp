@@ -1,0 +1,409 @@
+// C-ABI entry points (include/bdeg.h).
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <thread>
+#include <vector>
+
+#include "api_internal.hpp"
+#include "runtime.hpp"
+
+using namespace bdeg;
+
+namespace bdeg {
+
+static bdeg_u128 to_u128(u128 v) { return bdeg_u128{(uint64_t)v, (uint64_t)(v >> 64)}; }
+
+// Host prologue for one input system.  Fills `res` and, when device work is
+// needed, `hs` (returns true).
+bool prepare_one(const int64_t *A, int m, int n, uint64_t seed, int lift_bits, int index, bdeg_result &res,
+                 HostSys &hs) {
+  memset(&res, 0, sizeof res);
+  if (!A || m < 1 || n < 1 || n > BDEG_MAX_N || lift_bits < 2 || lift_bits > 30) {
+    res.status = BDEG_E_ARG;
+    return false;
+  }
+  KernelPoints kp = kernel_points(A, m, n);
+  if (kp.status != BDEG_OK) {
+    res.status = kp.status;
+    return false;
+  }
+  res.k = kp.k;
+  res.rank = kp.rank;
+  res.flags = kp.flags;
+  res.components = to_u128(kp.comps);
+  if (kp.k == 0) {
+    res.nvol = bdeg_u128{1, 0};
+    res.status = BDEG_OK;
+    return false;
+  }
+  const int N = n + 1;
+  if (kp.k > BDEG_MAX_K) {
+    res.status = BDEG_E_TOO_LARGE;
+    return false;
+  }
+  uint64_t cand = binom_u64(N, kp.k + 1);
+  if (cand >= (1ull << 63)) {
+    res.status = BDEG_E_TOO_LARGE;
+    return false;
+  }
+  res.candidates = cand;
+  if (!device_bounds_ok(kp.pts.data(), N, kp.k, (1ull << lift_bits) - 1)) {
+    res.status = BDEG_E_OVERFLOW;
+    return false;
+  }
+  hs.input_index = index;
+  hs.N = N;
+  hs.k = kp.k;
+  hs.lift_bits = lift_bits;
+  hs.attempt = 0;
+  hs.seed = seed;
+  hs.pts = std::move(kp.pts);
+  res.status = BDEG_PENDING;
+  return true;
+}
+
+int prepare_many(const int64_t *A_concat, const int32_t *m, const int32_t *n, int count, uint64_t seed,
+                 int lift_bits, std::vector<bdeg_result> &res, std::vector<HostSys> &dev) {
+  res.assign(count, bdeg_result{});
+  std::vector<size_t> off(count + 1, 0);
+  for (int s = 0; s < count; s++) {
+    int64_t mm = m[s], nn = n[s];
+    off[s + 1] = off[s] + (size_t)(mm > 0 && nn > 0 ? mm * nn : 0);
+  }
+  std::vector<HostSys> hs(count);
+  std::vector<char> need(count, 0);
+  auto work = [&](int lo, int hi) {
+    for (int s = lo; s < hi; s++)
+      need[s] = prepare_one(A_concat + off[s], m[s], n[s], seed, lift_bits, s, res[s], hs[s]);
+  };
+  int nt = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
+  if (count < 64) nt = 1;
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; t++) th.emplace_back(work, (int)((int64_t)count * t / nt), (int)((int64_t)count * (t + 1) / nt));
+  work(0, (int)((int64_t)count / nt));
+  for (auto &x : th) x.join();
+  dev.clear();
+  for (int s = 0; s < count; s++)
+    if (need[s]) dev.push_back(std::move(hs[s]));
+  return BDEG_OK;
+}
+
+// Run device systems to completion: tie retries redraw the lifting of the
+// tied systems only.  `first` (optional) is an already-launched job holding
+// all of `dev` in order.
+int finish_device(Device *D, std::vector<HostSys> &dev, std::vector<bdeg_result> &res, Job *first,
+                  DevCounters *cnt_out) {
+  std::vector<int> pending(dev.size());
+  for (size_t i = 0; i < dev.size(); i++) pending[i] = (int)i;
+  Job local;
+  for (int round = 0; !pending.empty(); round++) {
+    Job *job = (round == 0 && first) ? first : &local;
+    std::vector<HostSys> subset;
+    if (!(round == 0 && first)) {
+      for (int i : pending) subset.push_back(dev[i]);
+      uint64_t total = 0;
+      int kmax = 1;
+      for (auto &h : subset) {
+        total += binom_u64(h.N, h.k + 1);
+        kmax = std::max(kmax, h.k);
+      }
+      job_build_seeded(*job, subset, choose_max_cost(total, default_waves(kmax, 4)));
+      int rc = job_upload(*job);
+      if (rc) return rc;
+      rc = job_launch(*job, D->stream);
+      if (rc) return rc;
+    }
+    std::vector<SysAcc> acc;
+    DevCounters cnt;
+    int rc = job_collect(*job, D->stream, acc, &cnt);
+    if (rc) return rc;
+    if (round == 0 && cnt_out) *cnt_out = cnt;
+    std::vector<int> next;
+    for (size_t q = 0; q < pending.size(); q++) {
+      HostSys &h = dev[pending[q]];
+      bdeg_result &r = res[h.input_index];
+      r.attempts = (int32_t)h.attempt + 1;
+      if (acc[q].tie) {
+        if (h.attempt + 1 >= BDEG_MAX_ATTEMPTS) {
+          r.status = BDEG_E_TIE;
+          continue;
+        }
+        h.attempt++;
+        next.push_back(pending[q]);
+        continue;
+      }
+      r.nvol = bdeg_u128{acc[q].lo, acc[q].hi};
+      r.cells = acc[q].cells;
+      r.status = BDEG_OK;
+    }
+    pending.swap(next);
+  }
+  return BDEG_OK;
+}
+
+static int first_error(const std::vector<bdeg_result> &res) {
+  for (auto &r : res)
+    if (r.status != BDEG_OK) return r.status;
+  return BDEG_OK;
+}
+
+} // namespace bdeg
+
+struct bdeg_batch {
+  std::vector<bdeg_result> res;
+  std::vector<HostSys> dev;
+  Job job;
+  // the device pass is two captured graphs: clear + lift, then the
+  // enumeration, so that HIP events between them time the enumeration alone
+  hipGraph_t graph_pre = nullptr, graph_enum = nullptr;
+  hipGraphExec_t exec_pre = nullptr, exec_enum = nullptr;
+  hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_k0 = nullptr, ev_k1 = nullptr;
+  bool launched = false;
+  bdeg_stats stats{};
+};
+
+extern "C" {
+
+int bdeg_init(int32_t device) { return device_select(device); }
+
+const char *bdeg_strerror(int code) {
+  switch (code) {
+    case BDEG_OK: return "ok";
+    case BDEG_PENDING: return "pending";
+    case BDEG_E_ARG: return "invalid argument";
+    case BDEG_E_OVERFLOW: return "integer bound exceeded (host int64 algebra or device minor bound)";
+    case BDEG_E_TOO_LARGE: return "problem too large (k above the device limit or too many candidates)";
+    case BDEG_E_TIE: return "no generic lifting found";
+    case BDEG_E_DEVICE: return "HIP device error or no device";
+    case BDEG_E_NOMEM: return "out of memory";
+    case BDEG_E_STATE: return "invalid state";
+    default: return "unknown error";
+  }
+}
+
+int bdeg_kernel_points(const int64_t *A, int32_t m, int32_t n, int32_t *k, int32_t *rank, bdeg_u128 *components,
+                       int32_t *points) {
+  if (!A || !k || !rank || !components || !points || m < 1 || n < 1 || n > BDEG_MAX_N) return BDEG_E_ARG;
+  KernelPoints kp = kernel_points(A, m, n);
+  if (kp.status != BDEG_OK) return kp.status;
+  *k = kp.k;
+  *rank = kp.rank;
+  *components = to_u128(kp.comps);
+  if (!kp.pts.empty()) memcpy(points, kp.pts.data(), kp.pts.size() * sizeof(int32_t));
+  return BDEG_OK;
+}
+
+int bdeg_degree_batch(const int64_t *A_concat, const int32_t *m, const int32_t *n, int32_t count, uint64_t seed,
+                      int32_t lift_bits, bdeg_result *out) {
+  if (!A_concat || !m || !n || !out || count < 1) return BDEG_E_ARG;
+  std::vector<bdeg_result> res;
+  std::vector<HostSys> dev;
+  prepare_many(A_concat, m, n, count, seed, lift_bits, res, dev);
+  if (!dev.empty()) {
+    int st;
+    Device *D = device_get(&st);
+    if (!D) {
+      for (auto &h : dev) res[h.input_index].status = st;
+    } else {
+      std::lock_guard<std::mutex> lk(D->mu);
+      int rc = finish_device(D, dev, res, nullptr, nullptr);
+      if (rc)
+        for (auto &h : dev)
+          if (res[h.input_index].status == BDEG_PENDING) res[h.input_index].status = rc;
+    }
+  }
+  memcpy(out, res.data(), res.size() * sizeof(bdeg_result));
+  return first_error(res);
+}
+
+int bdeg_degree(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int32_t lift_bits, bdeg_result *out) {
+  if (!A || !out) return BDEG_E_ARG;
+  return bdeg_degree_batch(A, &m, &n, 1, seed, lift_bits, out);
+}
+
+int bdeg_batch_create(const int64_t *A_concat, const int32_t *m, const int32_t *n, int32_t count, uint64_t seed,
+                      int32_t lift_bits, bdeg_batch **out) {
+  if (!A_concat || !m || !n || !out || count < 1) return BDEG_E_ARG;
+  int st;
+  Device *D = device_get(&st);
+  if (!D) return st;
+  bdeg_batch *b = new bdeg_batch();
+  prepare_many(A_concat, m, n, count, seed, lift_bits, b->res, b->dev);
+  std::lock_guard<std::mutex> lk(D->mu);
+  if (!b->dev.empty()) {
+    uint64_t total = 0;
+    int kmax = 1;
+    for (auto &h : b->dev) {
+      total += binom_u64(h.N, h.k + 1);
+      kmax = std::max(kmax, h.k);
+    }
+    job_build_seeded(b->job, b->dev, choose_max_cost(total, default_waves(kmax, 4)));
+    int rc = job_upload(b->job);
+    if (rc) {
+      delete b;
+      return rc;
+    }
+  }
+  if (hipEventCreate(&b->ev_t0) != hipSuccess || hipEventCreate(&b->ev_t1) != hipSuccess ||
+      hipEventCreate(&b->ev_k0) != hipSuccess || hipEventCreate(&b->ev_k1) != hipSuccess) {
+    delete b;
+    return BDEG_E_DEVICE;
+  }
+  // capture clear + lift and the enumeration once each; replay per run
+  if (!b->dev.empty()) {
+    auto capture = [&](bool pre, hipGraph_t *g, hipGraphExec_t *x) {
+      if (hipStreamBeginCapture(D->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+      int rc = pre ? job_launch_pre(b->job, D->stream) : job_launch_enum(b->job, D->stream);
+      hipGraph_t gg = nullptr;
+      hipError_t e = hipStreamEndCapture(D->stream, &gg);
+      if (rc == BDEG_OK && e == hipSuccess && gg && hipGraphInstantiate(x, gg, nullptr, nullptr, 0) == hipSuccess) {
+        *g = gg;
+        return true;
+      }
+      if (gg) (void)hipGraphDestroy(gg);
+      *x = nullptr;
+      (void)hipGetLastError();
+      return false;
+    };
+    if (!capture(true, &b->graph_pre, &b->exec_pre) || !capture(false, &b->graph_enum, &b->exec_enum)) {
+      if (b->exec_pre) (void)hipGraphExecDestroy(b->exec_pre);
+      if (b->graph_pre) (void)hipGraphDestroy(b->graph_pre);
+      b->exec_pre = b->exec_enum = nullptr;
+      b->graph_pre = b->graph_enum = nullptr;
+    }
+  }
+  *out = b;
+  return BDEG_OK;
+}
+
+int bdeg_batch_run(bdeg_batch *b) {
+  if (!b) return BDEG_E_ARG;
+  int st;
+  Device *D = device_get(&st);
+  if (!D) return st;
+  if (b->dev.empty()) {
+    b->launched = true;
+    return BDEG_OK;
+  }
+  std::lock_guard<std::mutex> lk(D->mu);
+  // every run starts from attempt 0 (same liftings as the captured graph)
+  for (auto &h : b->dev) h.attempt = 0;
+  if (hipEventRecord(b->ev_t0, D->stream) != hipSuccess) return BDEG_E_DEVICE;
+  if (b->exec_pre && b->exec_enum) {
+    if (hipGraphLaunch(b->exec_pre, D->stream) != hipSuccess) return BDEG_E_DEVICE;
+    if (hipEventRecord(b->ev_k0, D->stream) != hipSuccess) return BDEG_E_DEVICE;
+    if (hipGraphLaunch(b->exec_enum, D->stream) != hipSuccess) return BDEG_E_DEVICE;
+    if (hipEventRecord(b->ev_k1, D->stream) != hipSuccess) return BDEG_E_DEVICE;
+  } else {
+    int rc = job_launch(b->job, D->stream, b->ev_k0, b->ev_k1);
+    if (rc) return rc;
+  }
+  if (hipEventRecord(b->ev_t1, D->stream) != hipSuccess) return BDEG_E_DEVICE;
+  b->launched = true;
+  return BDEG_OK;
+}
+
+int bdeg_batch_results(bdeg_batch *b, bdeg_result *out) {
+  if (!b || !out) return BDEG_E_ARG;
+  if (!b->launched) return BDEG_E_STATE;
+  if (!b->dev.empty()) {
+    int st;
+    Device *D = device_get(&st);
+    if (!D) return st;
+    std::lock_guard<std::mutex> lk(D->mu);
+    if (hipEventSynchronize(b->ev_t1) != hipSuccess) return BDEG_E_DEVICE;
+    float t = 0, k = 0;
+    (void)hipEventElapsedTime(&t, b->ev_t0, b->ev_t1);
+    (void)hipEventElapsedTime(&k, b->ev_k0, b->ev_k1);
+    DevCounters cnt{};
+    int rc = finish_device(D, b->dev, b->res, &b->job, &cnt);
+    if (rc) return rc;
+    for (int t = 0; t < BDEG_MAX_K; t++) b->stats.nodes[t] = cnt.nodes[t];
+    b->stats.pruned = cnt.pruned;
+    b->stats.leaves = cnt.leaves;
+    b->stats.tiles = cnt.tiles;
+    b->stats.kernel_ms = k;
+    b->stats.total_ms = t;
+  }
+  b->launched = false;
+  memcpy(out, b->res.data(), b->res.size() * sizeof(bdeg_result));
+  return first_error(b->res);
+}
+
+int bdeg_batch_stats(const bdeg_batch *b, bdeg_stats *out) {
+  if (!b || !out) return BDEG_E_ARG;
+  *out = b->stats;
+  return BDEG_OK;
+}
+
+int bdeg_batch_destroy(bdeg_batch *b) {
+  if (!b) return BDEG_E_ARG;
+  int st;
+  Device *D = device_get(&st);
+  if (D) {
+    std::lock_guard<std::mutex> lk(D->mu);
+    (void)hipStreamSynchronize(D->stream);
+    if (b->exec_pre) (void)hipGraphExecDestroy(b->exec_pre);
+    if (b->exec_enum) (void)hipGraphExecDestroy(b->exec_enum);
+    if (b->graph_pre) (void)hipGraphDestroy(b->graph_pre);
+    if (b->graph_enum) (void)hipGraphDestroy(b->graph_enum);
+    if (b->ev_t0) (void)hipEventDestroy(b->ev_t0);
+    if (b->ev_t1) (void)hipEventDestroy(b->ev_t1);
+    if (b->ev_k0) (void)hipEventDestroy(b->ev_k0);
+    if (b->ev_k1) (void)hipEventDestroy(b->ev_k1);
+    b->job.release();
+  }
+  delete b;
+  return BDEG_OK;
+}
+
+int bdeg_nvol_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, uint64_t rank_lo,
+                     uint64_t rank_hi, bdeg_u128 *nvol, int32_t *tie, uint64_t *cells) {
+  if (!points || !heights || !nvol || !tie || k < 1 || k > BDEG_MAX_K || N < k + 1 || N > 64) return BDEG_E_ARG;
+  int64_t hmin = heights[0], hmax = heights[0];
+  for (int j = 0; j < N; j++) {
+    if (heights[j] >= (1ll << 40) || heights[j] <= -(1ll << 40)) return BDEG_E_ARG;
+    hmin = std::min(hmin, heights[j]);
+    hmax = std::max(hmax, heights[j]);
+  }
+  if (!device_bounds_ok(points, N, k, (uint64_t)(hmax - hmin))) return BDEG_E_OVERFLOW;
+  int st;
+  Device *D = device_get(&st);
+  if (!D) return st;
+  std::lock_guard<std::mutex> lk(D->mu);
+  static Job job; // scratch job reused across calls (guarded by the device mutex)
+  job.sys.clear();
+  job.tiles.clear();
+  SysDesc d;
+  d.N = N;
+  d.k = k;
+  d.pt_off = 0;
+  d.ht_off = 0;
+  d.lift_bits = 0;
+  d.npad_log2 = N <= 8 ? 3 : N <= 16 ? 4 : N <= 32 ? 5 : 6;
+  d.lift_key = 0;
+  job.sys.push_back(d);
+  job.pts.assign(points, points + (size_t)N * k);
+  job.heights.assign(heights, heights + N);
+  job.explicit_heights = true;
+  job.kmax = k;
+  uint64_t total = binom_u64(N, k + 1);
+  uint64_t hi = std::min(rank_hi, total), lo = std::min(rank_lo, hi);
+  tiles_range(N, k, 0, lo, hi, choose_max_cost(hi - lo, default_waves(k, 4)), job.tiles);
+  std::stable_sort(job.tiles.begin(), job.tiles.end(), [](const Tile &a, const Tile &b) { return a.cost > b.cost; });
+  int rc = job_upload(job);
+  if (rc) return rc;
+  rc = job_launch(job, D->stream);
+  if (rc) return rc;
+  std::vector<SysAcc> acc;
+  rc = job_collect(job, D->stream, acc, nullptr);
+  if (rc) return rc;
+  *nvol = bdeg_u128{acc[0].lo, acc[0].hi};
+  *tie = (int32_t)acc[0].tie;
+  if (cells) *cells = acc[0].cells;
+  return BDEG_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,97 @@
+// Internal structures shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/bdeg.h"
+
+namespace bdeg {
+
+typedef unsigned __int128 u128;
+typedef __int128 i128;
+
+// Per-system device descriptor.  Points are int32 (k coordinates each),
+// heights int64; both live in flat device arrays at the given offsets.
+struct SysDesc {
+  int32_t N;         // points (n + 1), N <= 64
+  int32_t k;         // spatial dimension
+  int32_t pt_off;    // first int32 of the N x k points
+  int32_t ht_off;    // first int64 of the N heights
+  int32_t lift_bits; // heights uniform in [0, 2^lift_bits)
+  int32_t npad_log2; // lanes per point group: 8, 16, 32 or 64
+  uint64_t lift_key; // counter-based lifting key for the current attempt
+};
+
+// A work unit: the subtree of candidates that contain the prefix `mask` as
+// their top elements (colex), i.e. all (k+1)-subsets whose largest elements
+// are exactly the set bits of mask and whose remaining elements lie below the
+// lowest set bit.
+struct Tile {
+  uint64_t mask;
+  uint32_t sys;
+  uint32_t cost; // subtree size estimate, saturated to 2^32-1
+};
+
+// Per-system device accumulators (sum of |det| of lower facets, as a 128-bit
+// value in two 64-bit words, cell count and the tie flag).
+struct SysAcc {
+  uint64_t lo, hi;
+  uint64_t cells;
+  uint32_t tie;
+  uint32_t pad;
+};
+
+// Device-wide counters (zeroed per run).
+struct DevCounters {
+  uint64_t nodes[BDEG_MAX_K]; // nodes created per depth
+  uint64_t pruned, leaves, tiles;
+  uint32_t next_tile; // dynamic work queue head
+  uint32_t pad;
+};
+
+// ------------------------------------------------------------ host algebra
+struct KernelPoints {
+  int status = BDEG_OK;
+  int k = 0, rank = 0, m = 0, n = 0;
+  u128 comps = 0;
+  uint32_t flags = 0;
+  std::vector<int32_t> pts; // (n+1) x k, point 0 = origin
+};
+KernelPoints kernel_points(const int64_t *A, int m, int n);
+
+// Device certification: every Bareiss quantity of the device path fits the
+// narrow types (spatial minors int32, height minors int64, products in 96 bits).
+// `height_span` is max(h) - min(h) over the points.
+bool device_bounds_ok(const int32_t *pts, int N, int k, uint64_t height_span);
+
+// ------------------------------------------------------------ tiling
+uint64_t binom_u64(int n, int r); // saturates at UINT64_MAX
+// Cover all (k+1)-subsets of N points with subtrees of at most `max_cost`
+// candidates where possible (never deeper than k points chosen).
+void tiles_full(int N, int k, uint32_t sys, uint64_t max_cost, std::vector<Tile> &out);
+// Exactly the candidates with colex rank in [lo, hi).
+// Subtrees fully inside the range are further split down to max_cost.
+void tiles_range(int N, int k, uint32_t sys, uint64_t lo, uint64_t hi, uint64_t max_cost, std::vector<Tile> &out);
+
+// ------------------------------------------------------------ lifting
+uint64_t lift_key(uint64_t seed, uint32_t sys_index, uint32_t attempt);
+
+// ------------------------------------------------------------ kernels (kernels.hip)
+struct LaunchShape {
+  int blocks = 0;
+  int waves_per_block = 4;
+};
+// Launch helpers; all asynchronous on `stream` (a hipStream_t).
+int launch_lift(void *stream, const SysDesc *d_sys, const int32_t *d_active, int n_active,
+                int64_t *d_heights);
+int launch_clear(void *stream, SysAcc *d_acc, int n_sys, DevCounters *d_cnt);
+int launch_enumerate(void *stream, const SysDesc *d_sys, const int32_t *d_pts,
+                     const int64_t *d_heights, const Tile *d_tiles, uint32_t n_tiles, SysAcc *d_acc,
+                     DevCounters *d_cnt, int kmax, LaunchShape shape);
+int device_cu_count();
+int max_enum_blocks(int kmax, int waves_per_block); // occupancy-derived persistent grid
+
+} // namespace bdeg

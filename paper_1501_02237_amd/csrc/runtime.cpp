@@ -1,0 +1,180 @@
+// Host runtime: one device context per process, device-resident jobs.
+#include "runtime.hpp"
+
+#include <stdlib.h>
+
+#include <algorithm>
+
+namespace bdeg {
+
+static Device g_device;
+static std::once_flag g_once;
+static int g_status = BDEG_E_DEVICE;
+static int g_requested = -1;
+
+int device_select(int dev) {
+  if (g_device.dev >= 0) return BDEG_E_STATE;
+  g_requested = dev;
+  return BDEG_OK;
+}
+
+Device *device_get(int *status) {
+  std::call_once(g_once, [] {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return;
+    int dev = 0;
+    if (g_requested >= 0) {
+      if (g_requested >= count) return;
+      dev = g_requested;
+    } else {
+      const char *env = getenv("BDEG_DEVICE");
+      if (env) dev = atoi(env);
+      else if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+      if (dev < 0 || dev >= count) return;
+    }
+    if (hipSetDevice(dev) != hipSuccess) return;
+    if (hipStreamCreateWithFlags(&g_device.stream, hipStreamNonBlocking) != hipSuccess) return;
+    g_device.dev = dev;
+    g_device.cus = device_cu_count();
+    g_status = BDEG_OK;
+  });
+  if (status) *status = g_status;
+  if (g_status != BDEG_OK) return nullptr;
+  (void)hipSetDevice(g_device.dev);
+  return &g_device;
+}
+
+int default_waves(int kmax, int waves_per_block) {
+  int blocks = max_enum_blocks(kmax, waves_per_block);
+  return blocks > 0 ? blocks * waves_per_block : 1024;
+}
+
+// Subtree size cap: about 16 work units per resident wavefront, never below
+// 256 candidates (a unit re-derives its prefix, which costs a few levels).
+uint64_t choose_max_cost(uint64_t total, int waves) {
+  uint64_t per = total / ((uint64_t)(waves > 0 ? waves : 1) * 16);
+  return per < 256 ? 256 : per;
+}
+
+static int npad_log2_for(int N) {
+  if (N <= 8) return 3;
+  if (N <= 16) return 4;
+  if (N <= 32) return 5;
+  return 6;
+}
+
+void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t max_cost) {
+  job.sys.clear();
+  job.pts.clear();
+  job.tiles.clear();
+  job.kmax = 0;
+  job.explicit_heights = false;
+  int ht = 0;
+  for (size_t s = 0; s < systems.size(); s++) {
+    const HostSys &h = systems[s];
+    SysDesc d;
+    d.N = h.N;
+    d.k = h.k;
+    d.pt_off = (int32_t)job.pts.size();
+    d.ht_off = ht;
+    d.lift_bits = h.lift_bits;
+    d.npad_log2 = npad_log2_for(h.N);
+    d.lift_key = lift_key(h.seed, (uint32_t)h.input_index, h.attempt);
+    job.sys.push_back(d);
+    job.pts.insert(job.pts.end(), h.pts.begin(), h.pts.end());
+    ht += h.N;
+    job.kmax = std::max(job.kmax, h.k);
+    tiles_full(h.N, h.k, (uint32_t)s, max_cost, job.tiles);
+  }
+  std::stable_sort(job.tiles.begin(), job.tiles.end(), [](const Tile &a, const Tile &b) { return a.cost > b.cost; });
+  job.heights.assign(ht, 0);
+}
+
+template <typename T>
+static int grow(T **ptr, size_t *cap, size_t need) {
+  if (need == 0) need = 1;
+  if (*cap >= need) return BDEG_OK;
+  if (*ptr) (void)hipFree(*ptr);
+  *ptr = nullptr;
+  *cap = 0;
+  size_t n = need + need / 4;
+  if (hipMalloc((void **)ptr, n * sizeof(T)) != hipSuccess) {
+    *ptr = nullptr;
+    return BDEG_E_NOMEM;
+  }
+  *cap = n;
+  return BDEG_OK;
+}
+
+int job_upload(Job &job) {
+  int rc;
+  if ((rc = grow(&job.d_sys, &job.cap_sys, job.sys.size())) ||
+      (rc = grow(&job.d_pts, &job.cap_pts, job.pts.size())) ||
+      (rc = grow(&job.d_hts, &job.cap_hts, job.heights.size())) ||
+      (rc = grow(&job.d_tiles, &job.cap_tiles, job.tiles.size())))
+    return rc;
+  static_assert(sizeof(SysAcc) == 32, "SysAcc layout");
+  if ((rc = grow(&job.d_acc, &job.cap_acc, job.sys.size()))) return rc;
+  if (!job.d_cnt && hipMalloc((void **)&job.d_cnt, sizeof(DevCounters)) != hipSuccess) return BDEG_E_NOMEM;
+  if (hipMemcpy(job.d_sys, job.sys.data(), job.sys.size() * sizeof(SysDesc), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(job.d_pts, job.pts.data(), job.pts.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(job.d_tiles, job.tiles.data(), job.tiles.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess)
+    return BDEG_E_DEVICE;
+  if (job.explicit_heights &&
+      hipMemcpy(job.d_hts, job.heights.data(), job.heights.size() * sizeof(int64_t), hipMemcpyHostToDevice) !=
+          hipSuccess)
+    return BDEG_E_DEVICE;
+  return BDEG_OK;
+}
+
+int job_launch_pre(Job &job, hipStream_t stream) {
+  int rc = launch_clear(stream, job.d_acc, (int)job.sys.size(), job.d_cnt);
+  if (rc) return rc;
+  if (!job.explicit_heights) rc = launch_lift(stream, job.d_sys, nullptr, (int)job.sys.size(), job.d_hts);
+  return rc;
+}
+
+int job_launch_enum(Job &job, hipStream_t stream) {
+  return launch_enumerate(stream, job.d_sys, job.d_pts, job.d_hts, job.d_tiles, (uint32_t)job.tiles.size(),
+                          job.d_acc, job.d_cnt, job.kmax, job.shape);
+}
+
+int job_launch(Job &job, hipStream_t stream, hipEvent_t e0, hipEvent_t e1) {
+  int rc = job_launch_pre(job, stream);
+  if (rc) return rc;
+  if (e0 && hipEventRecord(e0, stream) != hipSuccess) return BDEG_E_DEVICE;
+  if ((rc = job_launch_enum(job, stream))) return rc;
+  if (e1 && hipEventRecord(e1, stream) != hipSuccess) return BDEG_E_DEVICE;
+  return BDEG_OK;
+}
+
+int job_collect(Job &job, hipStream_t stream, std::vector<SysAcc> &acc, DevCounters *cnt) {
+  acc.resize(job.sys.size());
+  if (!acc.empty() &&
+      hipMemcpyAsync(acc.data(), job.d_acc, acc.size() * sizeof(SysAcc), hipMemcpyDeviceToHost, stream) != hipSuccess)
+    return BDEG_E_DEVICE;
+  if (cnt && hipMemcpyAsync(cnt, job.d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, stream) != hipSuccess)
+    return BDEG_E_DEVICE;
+  if (hipStreamSynchronize(stream) != hipSuccess) return BDEG_E_DEVICE;
+  return BDEG_OK;
+}
+
+void Job::release() {
+  if (d_sys) (void)hipFree(d_sys);
+  if (d_pts) (void)hipFree(d_pts);
+  if (d_hts) (void)hipFree(d_hts);
+  if (d_tiles) (void)hipFree(d_tiles);
+  if (d_acc) (void)hipFree(d_acc);
+  if (d_cnt) (void)hipFree(d_cnt);
+  d_sys = nullptr;
+  d_pts = nullptr;
+  d_hts = nullptr;
+  d_tiles = nullptr;
+  d_acc = nullptr;
+  d_cnt = nullptr;
+  cap_sys = cap_pts = cap_hts = cap_tiles = cap_acc = 0;
+}
+
+Job::~Job() { release(); }
+
+} // namespace bdeg

@@ -1,0 +1,69 @@
+// Host runtime: device context, device-resident jobs, graph replay, tie retry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
+
+#include "bdeg_internal.hpp"
+
+namespace bdeg {
+
+struct Device {
+  int dev = -1;
+  hipStream_t stream = nullptr;
+  int cus = 0;
+  std::mutex mu; // serialises use of `stream` and the shared scratch job
+};
+// Process-wide device context; status receives BDEG_OK or BDEG_E_DEVICE.
+Device *device_get(int *status);
+int device_select(int dev);
+
+// Host side of one device system (k >= 1, certified bounds).
+struct HostSys {
+  int input_index;   // index in the caller's batch
+  int N, k, lift_bits;
+  uint32_t attempt;
+  uint64_t seed;
+  std::vector<int32_t> pts; // N x k
+};
+
+// Device buffers for a set of systems and their tiles.
+struct Job {
+  std::vector<SysDesc> sys;
+  std::vector<int32_t> pts;
+  std::vector<Tile> tiles;
+  int kmax = 0;
+  bool explicit_heights = false;
+  std::vector<int64_t> heights; // when explicit
+
+  SysDesc *d_sys = nullptr;
+  int32_t *d_pts = nullptr;
+  int64_t *d_hts = nullptr;
+  Tile *d_tiles = nullptr;
+  SysAcc *d_acc = nullptr;
+  DevCounters *d_cnt = nullptr;
+  size_t cap_sys = 0, cap_pts = 0, cap_hts = 0, cap_tiles = 0, cap_acc = 0;
+
+  LaunchShape shape;
+  ~Job();
+  void release();
+};
+
+// Build device descriptors and tiles for `systems` (seeded lifting) into job.
+void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t max_cost);
+// Upload (growing buffers as needed).
+int job_upload(Job &job);
+// Enqueue clear + lift (pre) and the enumeration; job_launch does both.
+int job_launch_pre(Job &job, hipStream_t stream);
+int job_launch_enum(Job &job, hipStream_t stream);
+int job_launch(Job &job, hipStream_t stream, hipEvent_t ev_kernel_start = nullptr,
+               hipEvent_t ev_kernel_end = nullptr);
+// Copy accumulators back (synchronous on stream).
+int job_collect(Job &job, hipStream_t stream, std::vector<SysAcc> &acc, DevCounters *cnt);
+
+uint64_t choose_max_cost(uint64_t total_candidates, int waves);
+int default_waves(int kmax, int waves_per_block);
+
+} // namespace bdeg

@@ -1,0 +1,91 @@
+// Work decomposition of the candidate space of one system.
+//
+// Candidates are the (k+1)-subsets {c_0 < ... < c_k} of the N points (the
+// brute-force search over all subsets of Section 4), numbered in colex order
+// rank = sum_i C(c_i, i+1).  Fixing the top elements c_k > ... > c_{k-L+1}
+// (a "prefix" of L elements, lowest element e) leaves C(e, k+1-L) completions
+// whose ranks form one contiguous interval; such a subtree is one device work
+// unit, described by the bit mask of its prefix.
+#include <stdint.h>
+
+#include <vector>
+
+#include "bdeg_internal.hpp"
+
+namespace bdeg {
+
+uint64_t binom_u64(int n, int r) {
+  if (r < 0 || n < 0 || r > n) return 0;
+  if (r > n - r) r = n - r;
+  u128 c = 1;
+  for (int i = 1; i <= r; i++) {
+    c = c * (u128)(n - r + i) / (u128)i;
+    if (c > (u128)UINT64_MAX) return UINT64_MAX;
+  }
+  return (uint64_t)c;
+}
+
+static inline uint32_t sat32(uint64_t x) { return x > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)x; }
+
+// prefix `mask` has L elements with lowest element e; its subtree has
+// C(e, k+1-L) candidates.  Split while larger than max_cost and fewer than k
+// points are fixed (a k-point prefix has at most e <= 63 leaves).
+static void split(int k, uint32_t sys, uint64_t mask, int L, int e, uint64_t max_cost,
+                  std::vector<Tile> &out) {
+  uint64_t cost = binom_u64(e, k + 1 - L);
+  if (cost == 0) return;
+  if (cost <= max_cost || L >= k) {
+    out.push_back(Tile{mask, sys, sat32(cost)});
+    return;
+  }
+  for (int c = e - 1; c >= k - L; c--) split(k, sys, mask | (1ull << c), L + 1, c, max_cost, out);
+}
+
+void tiles_full(int N, int k, uint32_t sys, uint64_t max_cost, std::vector<Tile> &out) {
+  if (max_cost == 0) max_cost = 1;
+  for (int b = N - 1; b >= k; b--) split(k, sys, 1ull << b, 1, b, max_cost, out);
+}
+
+// Ranks of the children of a node: the next element c (position i = k - L)
+// covers [base + C(c, i+1), base + C(c+1, i+1)).
+static void cover(int k, uint32_t sys, uint64_t mask, int L, int e, uint64_t base, uint64_t lo,
+                  uint64_t hi, uint64_t max_cost, std::vector<Tile> &out) {
+  const int i = k - L;
+  for (int c = i; c < e; c++) {
+    uint64_t start = base + binom_u64(c, i + 1);
+    uint64_t size = binom_u64(c, i);
+    uint64_t end = start + size;
+    if (end <= lo || start >= hi) continue;
+    uint64_t m2 = mask | (1ull << c);
+    if (lo <= start && end <= hi)
+      split(k, sys, m2, L + 1, c, max_cost, out);
+    else
+      cover(k, sys, m2, L + 1, c, start, lo, hi, max_cost, out);
+  }
+}
+
+void tiles_range(int N, int k, uint32_t sys, uint64_t lo, uint64_t hi, uint64_t max_cost,
+                 std::vector<Tile> &out) {
+  uint64_t total = binom_u64(N, k + 1);
+  if (hi > total) hi = total;
+  if (lo >= hi) return;
+  if (max_cost == 0) max_cost = 1;
+  cover(k, sys, 0, 0, N, 0, lo, hi, max_cost, out);
+}
+
+// Counter-based lifting key: SplitMix64's finaliser (Steele, Lea, Flood 2014)
+// over (seed, system, attempt), tagged with a library constant.
+static inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t lift_key(uint64_t seed, uint32_t sys_index, uint32_t attempt) {
+  const uint64_t LIB_TAG = 0xB0E6D0C5B0E6D0C5ull;
+  uint64_t z = seed ^ LIB_TAG ^ ((uint64_t)(sys_index + 1) * 0x9E3779B97F4A7C15ull) ^
+               ((uint64_t)(attempt + 1) * 0xD1B54A32D192ED03ull);
+  return mix64(mix64(z));
+}
+
+} // namespace bdeg

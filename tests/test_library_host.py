@@ -1,0 +1,115 @@
+"""CPU-only checks of the product library: it loads, exports every symbol the
+header declares, and its host prologue (rank, components, kernel points,
+argument checks, tiling bounds) agrees with the oracle and with mathematics.
+No device compute is called here."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+from sympy import Matrix
+
+import gen
+import oracle
+from oracle import algebra
+import paper_1501_02237_amd as bd
+
+
+def test_library_exports_every_header_symbol():
+    L = bd.lib()
+    names = bd.header_functions()
+    assert len(names) >= 16
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_strerror_covers_codes():
+    for c in (0, 1, -1, -2, -3, -4, -5, -6, -7):
+        assert bd.strerror(c) and "unknown" not in bd.strerror(c)
+
+
+def _check_kernel(A, k, rank, comps, P):
+    A = np.asarray(A)
+    m, n = A.shape
+    assert P.shape == (n + 1, k)
+    assert (P[0] == 0).all()
+    V = Matrix(P[1:].tolist())
+    assert (Matrix(A.tolist()) * V).is_zero_matrix
+    if k:
+        assert V.rank() == k
+        g = 0
+        for rows in itertools.combinations(range(n), k):
+            g = math.gcd(g, int(V.extract(list(rows), list(range(k))).det()))
+            if g == 1:
+                break
+        assert g == 1
+
+
+@pytest.mark.parametrize("idx", range(10))
+def test_kernel_points_vs_oracle(idx):
+    n = 8 + idx
+    k = 1 + idx % 5
+    A = gen.quiver_matrix(0x5EED0101, idx, n, n - k, 2, 3)
+    kk, rank, comps, P = bd.kernel_points(A)
+    ok, ocomps, _ = algebra.kernel_points(A.tolist())
+    assert (kk, comps) == (ok, ocomps)
+    assert rank == n - kk
+    _check_kernel(A, kk, rank, comps, P)
+
+
+@pytest.mark.parametrize("idx", range(8))
+def test_components_dense_and_rank_deficient(idx):
+    rng = gen.stream(0x5EED0102, idx, gen.PURPOSE_MATRIX)
+    m, n = 2 + idx % 3, 4 + idx % 3
+    A = [[rng.uniform_int(-4, 4) for _ in range(n)] for _ in range(m)]
+    if idx % 2:
+        A.append([2 * a - b for a, b in zip(A[0], A[1])])
+    kk, rank, comps, P = bd.kernel_points(np.array(A))
+    r, d, _ = algebra.smith_with_left_transform(A)
+    assert rank == r and comps == algebra.components(d)
+    _check_kernel(np.array(A), kk, rank, comps, P)
+
+
+def test_workload_kernels_are_small():
+    for s in (gen.cfg1_system(), gen.cfg2_system(), gen.cfg4_system()):
+        k, rank, comps, P = bd.kernel_points(s.A)
+        assert rank == s.m and comps == 1
+        assert np.abs(P).max() <= 8
+
+
+def test_zero_and_unimodular_systems():
+    k, rank, comps, P = bd.kernel_points(np.zeros((2, 4), dtype=np.int64))
+    assert (k, rank, comps) == (4, 0, 1)
+    assert abs(Matrix(P[1:].tolist()).det()) == 1
+    U = np.array([[1, 2, 0], [0, 1, 3], [0, 0, 1]], dtype=np.int64)
+    assert bd.kernel_points(U)[:3] == (0, 3, 1)
+
+
+def test_argument_errors():
+    with pytest.raises(bd.BdegError) as e:
+        bd.kernel_points(np.zeros((1, 64), dtype=np.int64))
+    assert e.value.code == bd.BDEG_E_ARG
+
+
+def test_host_overflow_is_reported():
+    # kernel vector of [1, -2^40]: entries around 2^40 fit int64 but not the int32 point format
+    A = np.array([[1, -(1 << 40)]], dtype=np.int64)
+    with pytest.raises(bd.BdegError) as e:
+        bd.kernel_points(A)
+    assert e.value.code == bd.BDEG_E_OVERFLOW
+
+
+def test_degree_without_device_fails_loudly():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present; covered by the gpu tests")
+    r = bd.degree(gen.cfg1_system().A, check=False)
+    assert r["status"] == bd.BDEG_E_DEVICE
+    assert r["k"] == 6  # host prologue still reported
+
+
+def test_degree_k0_needs_no_device():
+    # k = 0 is answered on the host (a finite set of points, nvol = 1)
+    r = bd.degree(np.array([[2, 1], [1, 1]], dtype=np.int64), check=False)
+    assert (r["status"], r["k"], r["comps"], r["nvol"]) == (0, 0, 1, 1)
