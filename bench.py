@@ -30,18 +30,78 @@ PEAK_ALU = 256 * 4 * 16 * 2.4e9  # 32-bit integer VALU lane-ops/s: CUs x SIMDs x
 
 
 def ops_per_launch(stats: dict, N: int, k: int) -> float:
-    """Algorithmic 32-bit integer operations of one enumeration launch (op
-    model: a spatial elimination entry 8 ops, a height entry 16, a leaf test
-    13 per other point; node counts from the device counters)."""
-    ops = 0.0
-    for t in range(1, k):
-        ops += stats["nodes"][t] * N * (8 * (k - t) + 16)
-    ops += stats["leaves"] * (N - k - 1) * 13
-    return ops
+    """Algorithmic 32-bit integer operations of one enumeration launch.
+
+    Op model (32-bit lane operations of the minimal instruction sequence; a
+    32 x 32 -> 64 multiply counts 2, a 64-bit add/shift 2):
+      spatial residual entry  8   (two products, a 64-bit difference, a shift, the inverse multiply)
+      height residual entry  24   (two 64-bit halves of two products each, shift-add, 64-bit inverse multiply, split)
+      leaf test per point    20   (two halves, carry fold, sign and zero tests)
+    Every node update runs on all N points; a leaf tests the N - k - 1 other points."""
+    sp = stats["spatial_updates"] + stats["ridges"]
+    ht = stats["inner_nodes"] + stats["ridges"]
+    return N * (8.0 * sp + 24.0 * ht) + 20.0 * (N - k - 1) * stats["leaves"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(q * len(xs)))]
+
+
+def serve_trace(bd, gen, count):
+    """Poisson arrivals (mean 200 req/s) of quiver-like systems, n ~ U[12,32],
+    k ~ U[4,9]: served by the continuous-batching engine vs plain sequential
+    solves (one bdeg_degree at a time, in arrival order)."""
+    log(f"[bench] serving: generating {count} requests")
+    trace = gen.cfg5_trace(count)
+    mats = [q.system.A for q in trace]
+    out = {}
+    # plain sequential solves: measured service times, FIFO queue simulated on the arrival times
+    plain, service = [], []
+    for A in mats:
+        t = time.perf_counter()
+        plain.append(bd.degree(A, seed=5, lift_bits=20))
+        service.append(time.perf_counter() - t)
+    free, lat_plain = 0.0, []
+    for q, sv in zip(trace, service):
+        free = max(free, q.arrival_s) + sv
+        lat_plain.append((free - q.arrival_s) * 1e3)
+    out["serve_plain_p50_ms"] = round(pct(lat_plain, 0.5), 3)
+    out["serve_plain_p99_ms"] = round(pct(lat_plain, 0.99), 3)
+    out["serve_plain_systems_per_s"] = count / sum(service)
+    # served, real time: submit at the arrival times
+    srv = bd.Server(256 << 20)
+    t0 = time.perf_counter()
+    tickets = []
+    for q, A in zip(trace, mats):
+        while time.perf_counter() - t0 < q.arrival_s:
+            pass
+        tickets.append(srv.submit(A, seed=5, lift_bits=20))
+    got = [srv.wait(t) for t in tickets]
+    t_end = time.perf_counter() - t0
+    lat = [srv.latency_ms(t) for t in tickets]
+    srv.close()
+    assert all(g["nvol"] == p["nvol"] and g["status"] == 0 for g, p in zip(got, plain))
+    out["serve_p50_ms"] = round(pct(lat, 0.5), 3)
+    out["serve_p99_ms"] = round(pct(lat, 0.99), 3)
+    out["serve_trace_systems_per_s"] = count / t_end
+    # saturated: everything submitted at once, served vs plain
+    srv = bd.Server(256 << 20)
+    t = time.perf_counter()
+    tickets = [srv.submit(A, seed=5, lift_bits=20) for A in mats]
+    got = [srv.wait(x) for x in tickets]
+    sat = time.perf_counter() - t
+    srv.close()
+    assert all(g["nvol"] == p["nvol"] for g, p in zip(got, plain))
+    out["serve_saturated_systems_per_s"] = count / sat
+    log(f"[bench] serving: p50 {out['serve_p50_ms']} ms p99 {out['serve_p99_ms']} ms "
+        f"(plain sequential p50 {out['serve_plain_p50_ms']} p99 {out['serve_plain_p99_ms']}); "
+        f"saturated {count / sat:.0f} sys/s vs plain {out['serve_plain_systems_per_s']:.0f} sys/s")
+    return out
 
 
 def main():
@@ -51,6 +111,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=4000)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {a.gpus}); "
@@ -86,6 +147,7 @@ def main():
         assert r["status"] == 0 and r["nvol"] == ref["nvol"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    st = b.profile()  # work counters of the same pass (counting kernel variant, untimed)
     b.close()
     ms_step = dt * 1e3 / a.steps
     value = cand2 * a.steps / dt
@@ -95,8 +157,8 @@ def main():
     log(f"[bench] headline: {ms_step:.3f} ms/step, kernel {k_ms:.3f} ms, nvol={ref['nvol']}, "
         f"{value:.3e} cand/s, ops/launch {ops:.3e}")
 
-    extra = {"nvol": ref["nvol"], "kernel_ms": round(k_ms, 4), "leaves": st["leaves"], "nodes": st["nodes"][:k2],
-             "pruned": st["pruned"], "tiles": st["tiles"]}
+    extra = {"nvol": ref["nvol"], "kernel_ms": round(k_ms, 4), "leaves": st["leaves"], "ridges": st["ridges"],
+             "inner_nodes": st["inner_nodes"], "pruned": st["pruned"], "units": st["tiles"]}
     if not a.no_extras:
         # end-to-end plain solve (host prologue, tiling, copies, device pass)
         reps = 10
@@ -156,6 +218,9 @@ def main():
         extra["large36_kernel_ms"] = round(st4["kernel_ms"], 3)
         extra["large36_cand_per_s"] = cand4 / (st4["total_ms"] * 1e-3)
         log(f"[bench] n=36 k=10: nvol={r4['nvol']} kernel {st4['kernel_ms']:.2f} ms")
+
+        if a.serve_requests > 0:
+            extra.update(serve_trace(bd, gen, a.serve_requests))
 
     cpu = None
     if not a.no_cpu:

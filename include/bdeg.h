@@ -82,8 +82,9 @@ typedef struct {
 
 /* Device work counters of the last device run (for roofline accounting). */
 typedef struct {
-  uint64_t nodes[BDEG_MAX_K]; /* nodes[t]: subtree nodes created at depth t (t+1 points fixed),
-                                 1 <= t <= k-1; nodes[k-1] are the ridges (k points fixed) */
+  uint64_t ridges;            /* subtree nodes with k points fixed (each tests its candidates) */
+  uint64_t inner_nodes;       /* subtree nodes with 2..k-1 points fixed */
+  uint64_t spatial_updates;   /* spatial residual columns eliminated over all inner nodes */
   uint64_t pruned;            /* prefixes cut because the new point is affinely dependent */
   uint64_t leaves;            /* candidates tested with a nonzero determinant */
   uint64_t tiles;             /* work units processed */
@@ -124,7 +125,11 @@ int bdeg_degree_batch(const int64_t *A_concat, const int32_t *m, const int32_t *
  *                       lifting, enumeration) on the library stream; async.
  *   bdeg_batch_results  wait, redraw liftings of tied systems (uncaptured
  *                       reruns) until none ties, fill out[count].
- *   bdeg_batch_stats    counters and HIP-event times of the last run.
+ *   bdeg_batch_stats    HIP-event times of the last run, and the work counters
+ *                       of the last profiling pass.
+ *   bdeg_batch_profile  one extra synchronous device pass with the kernel
+ *                       variant that also counts its work (same lifting, same
+ *                       work); fills the counters of bdeg_batch_stats.
  *   bdeg_batch_destroy  free everything.
  */
 typedef struct bdeg_batch bdeg_batch;
@@ -133,6 +138,7 @@ int bdeg_batch_create(const int64_t *A_concat, const int32_t *m, const int32_t *
 int bdeg_batch_run(bdeg_batch *b);
 int bdeg_batch_results(bdeg_batch *b, bdeg_result *out);
 int bdeg_batch_stats(const bdeg_batch *b, bdeg_stats *out);
+int bdeg_batch_profile(bdeg_batch *b);
 int bdeg_batch_destroy(bdeg_batch *b);
 
 /*
@@ -166,7 +172,13 @@ int bdeg_kernel_points(const int64_t *A, int32_t m, int32_t n, int32_t *k, int32
  *   bdeg_serve_submit  copy A, queue the request, return a ticket (non-blocking).
  *   bdeg_serve_poll    BDEG_OK with *out filled (once), or BDEG_PENDING.
  *   bdeg_serve_wait    block until done, then as poll.
+ *   bdeg_serve_latency time from submit to completion of a finished request,
+ *                      in nanoseconds (BDEG_PENDING while it runs); valid
+ *                      until bdeg_serve_close.
  *   bdeg_serve_close   finish queued work, stop the engine, free everything.
+ * The budget bounds the device memory of admitted requests (a slot of about
+ * 4 KiB each plus their share of the per-step work-unit buffer); requests
+ * beyond it wait in arrival order.
  */
 typedef struct bdeg_server bdeg_server;
 int bdeg_serve_open(size_t device_mem_budget, bdeg_server **out);
@@ -174,7 +186,20 @@ int bdeg_serve_submit(bdeg_server *s, const int64_t *A, int32_t m, int32_t n, ui
                       int32_t lift_bits, uint64_t *ticket);
 int bdeg_serve_poll(bdeg_server *s, uint64_t ticket, bdeg_result *out);
 int bdeg_serve_wait(bdeg_server *s, uint64_t ticket, bdeg_result *out);
+int bdeg_serve_latency(bdeg_server *s, uint64_t ticket, uint64_t *submit_to_done_ns);
 int bdeg_serve_close(bdeg_server *s);
+
+/*
+ * Host only: the device work units for the candidates of N points in Z^k
+ * with colex rank in [rank_lo, rank_hi), each at most max_cost candidates
+ * where the subtree structure allows (0: the library's default for the
+ * current device is not used; pass the cap explicitly).  Each unit is
+ * reported as its colex rank interval [start, end): intervals[2u] = start,
+ * intervals[2u+1] = end, in the order the device takes them.  *n_units is
+ * always set; at most `cap` units are written (BDEG_E_NOMEM if more exist).
+ */
+int bdeg_plan_units(int32_t N, int32_t k, uint64_t rank_lo, uint64_t rank_hi, uint64_t max_cost,
+                    uint64_t *intervals, size_t cap, size_t *n_units);
 
 const char *bdeg_strerror(int code);
 

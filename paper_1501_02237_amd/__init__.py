@@ -60,14 +60,13 @@ class Result(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [
-        ("nodes", ctypes.c_uint64 * MAX_K), ("pruned", ctypes.c_uint64), ("leaves", ctypes.c_uint64),
-        ("tiles", ctypes.c_uint64), ("kernel_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
+        ("ridges", ctypes.c_uint64), ("inner_nodes", ctypes.c_uint64), ("spatial_updates", ctypes.c_uint64),
+        ("pruned", ctypes.c_uint64), ("leaves", ctypes.c_uint64), ("tiles", ctypes.c_uint64),
+        ("kernel_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
     ]
 
     def as_dict(self) -> dict:
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "nodes"}
-        d["nodes"] = list(self.nodes)
-        return d
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _lib = None
@@ -90,6 +89,7 @@ def lib() -> ctypes.CDLL:
         "bdeg_batch_run": ([P], ctypes.c_int),
         "bdeg_batch_results": ([P, P], ctypes.c_int),
         "bdeg_batch_stats": ([P, P], ctypes.c_int),
+        "bdeg_batch_profile": ([P], ctypes.c_int),
         "bdeg_batch_destroy": ([P], ctypes.c_int),
         "bdeg_nvol_points": ([P, P, I32, I32, U64, U64, P, P, P], ctypes.c_int),
         "bdeg_kernel_points": ([P, I32, I32, P, P, P, P], ctypes.c_int),
@@ -97,7 +97,9 @@ def lib() -> ctypes.CDLL:
         "bdeg_serve_submit": ([P, P, I32, I32, U64, I32, P], ctypes.c_int),
         "bdeg_serve_poll": ([P, U64, P], ctypes.c_int),
         "bdeg_serve_wait": ([P, U64, P], ctypes.c_int),
+        "bdeg_serve_latency": ([P, U64, P], ctypes.c_int),
         "bdeg_serve_close": ([P], ctypes.c_int),
+        "bdeg_plan_units": ([I32, I32, U64, U64, U64, P, SZ, P], ctypes.c_int),
         "bdeg_strerror": ([ctypes.c_int], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -169,6 +171,18 @@ def kernel_points(A) -> tuple[int, int, int, np.ndarray]:
     return k.value, rank.value, comps.value, pts[: (n + 1) * k.value].reshape(n + 1, k.value)
 
 
+def plan_units(N: int, k: int, rank_lo: int = 0, rank_hi: int | None = None, max_cost: int = 256) -> np.ndarray:
+    """Host-only: the device work units as colex rank intervals [start, end)."""
+    n = ctypes.c_size_t()
+    hi = U64_MAX if rank_hi is None else rank_hi
+    lib().bdeg_plan_units(N, k, rank_lo, hi, max_cost, None, 0, ctypes.byref(n))
+    buf = np.zeros(2 * max(n.value, 1), dtype=np.uint64)
+    rc = lib().bdeg_plan_units(N, k, rank_lo, hi, max_cost, buf.ctypes.data, n.value, ctypes.byref(n))
+    if rc != BDEG_OK:
+        raise BdegError(rc, "bdeg_plan_units")
+    return buf[: 2 * n.value].reshape(-1, 2)
+
+
 @dataclass
 class VolumeRange:
     nvol: int
@@ -215,6 +229,13 @@ class Batch:
         lib().bdeg_batch_stats(self._h, ctypes.byref(s))
         return s.as_dict()
 
+    def profile(self) -> dict:
+        """One extra device pass with the work-counting kernel variant."""
+        rc = lib().bdeg_batch_profile(self._h)
+        if rc != BDEG_OK:
+            raise BdegError(rc, "bdeg_batch_profile")
+        return self.stats()
+
     def close(self) -> None:
         if self._h:
             lib().bdeg_batch_destroy(self._h)
@@ -260,6 +281,16 @@ class Server:
         if rc != BDEG_OK and rc != r.status:
             raise BdegError(rc, "bdeg_serve_wait")
         return r.as_dict()
+
+    def latency_ms(self, ticket: int) -> float | None:
+        """Submit-to-completion time of a finished request (engine clock)."""
+        ns = ctypes.c_uint64()
+        rc = lib().bdeg_serve_latency(self._h, ticket, ctypes.byref(ns))
+        if rc == BDEG_PENDING:
+            return None
+        if rc != BDEG_OK:
+            raise BdegError(rc, "bdeg_serve_latency")
+        return ns.value * 1e-6
 
     def close(self) -> None:
         if self._h:

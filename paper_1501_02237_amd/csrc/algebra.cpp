@@ -195,8 +195,9 @@ KernelPoints kernel_points(const int64_t *A, int m, int n) {
 // product over the k+1 largest such factors.  A height residual expands along
 // the height column into at most k+1 height differences times such minors:
 // |.| <= (k+1) * span * Hs.  The device keeps spatial values in int32 and
-// height values in int64 and forms products in 128 bits, so it needs
-// Hs < 2^31 and (k+1) * span * Hs < 2^62.
+// splits heights as H1 * 2^31 + H0 so that every product is 32 x 32 -> 64 bits;
+// sums of two such products must fit int64, so it needs Hs < 2^31 and
+// (k+1) * span * Hs < 2^60.
 //
 // The same minors are also bounded column-wise (Hadamard on columns): the
 // all-ones column has norm <= sqrt(k+1) and coordinate column i has norm
@@ -235,11 +236,11 @@ bool device_bounds_ok(const int32_t *pts, int N, int k, uint64_t height_span) {
   }
   const u128 h2 = std::min(h2_rows, h2_cols);
   if (h2 >= lim) return false;
-  // ((k+1) * span)^2 * Hs^2 < 2^124
+  // ((k+1) * span)^2 * Hs^2 < 2^120
   u128 ks = (u128)(k + 1) * (u128)(height_span ? height_span : 1);
-  if (ks >= ((u128)1 << 62)) return false;
+  if (ks >= ((u128)1 << 60)) return false;
   u128 ks2 = ks * ks;
-  const u128 lim2 = (u128)1 << 124;
+  const u128 lim2 = (u128)1 << 120;
   if (h2 != 0 && ks2 > lim2 / h2) return false;
   return true;
 }

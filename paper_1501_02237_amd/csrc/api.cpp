@@ -104,12 +104,13 @@ int finish_device(Device *D, std::vector<HostSys> &dev, std::vector<bdeg_result>
     if (!(round == 0 && first)) {
       for (int i : pending) subset.push_back(dev[i]);
       uint64_t total = 0;
-      int kmax = 1;
+      int kmax = 1, kmin = 64;
       for (auto &h : subset) {
         total += binom_u64(h.N, h.k + 1);
         kmax = std::max(kmax, h.k);
+        kmin = std::min(kmin, h.k);
       }
-      job_build_seeded(*job, subset, choose_max_cost(total, default_waves(kmax, 4)));
+      job_build_seeded(*job, subset, choose_max_cost(total, default_waves(std::min(kmin, kmax), kmax, 4)));
       int rc = job_upload(*job);
       if (rc) return rc;
       rc = job_launch(*job, D->stream);
@@ -234,12 +235,13 @@ int bdeg_batch_create(const int64_t *A_concat, const int32_t *m, const int32_t *
   std::lock_guard<std::mutex> lk(D->mu);
   if (!b->dev.empty()) {
     uint64_t total = 0;
-    int kmax = 1;
+    int kmax = 1, kmin = 64;
     for (auto &h : b->dev) {
       total += binom_u64(h.N, h.k + 1);
       kmax = std::max(kmax, h.k);
+      kmin = std::min(kmin, h.k);
     }
-    job_build_seeded(b->job, b->dev, choose_max_cost(total, default_waves(kmax, 4)));
+    job_build_seeded(b->job, b->dev, choose_max_cost(total, default_waves(std::min(kmin, kmax), kmax, 4)));
     int rc = job_upload(b->job);
     if (rc) {
       delete b;
@@ -317,13 +319,8 @@ int bdeg_batch_results(bdeg_batch *b, bdeg_result *out) {
     float t = 0, k = 0;
     (void)hipEventElapsedTime(&t, b->ev_t0, b->ev_t1);
     (void)hipEventElapsedTime(&k, b->ev_k0, b->ev_k1);
-    DevCounters cnt{};
-    int rc = finish_device(D, b->dev, b->res, &b->job, &cnt);
+    int rc = finish_device(D, b->dev, b->res, &b->job, nullptr);
     if (rc) return rc;
-    for (int t = 0; t < BDEG_MAX_K; t++) b->stats.nodes[t] = cnt.nodes[t];
-    b->stats.pruned = cnt.pruned;
-    b->stats.leaves = cnt.leaves;
-    b->stats.tiles = cnt.tiles;
     b->stats.kernel_ms = k;
     b->stats.total_ms = t;
   }
@@ -335,6 +332,30 @@ int bdeg_batch_results(bdeg_batch *b, bdeg_result *out) {
 int bdeg_batch_stats(const bdeg_batch *b, bdeg_stats *out) {
   if (!b || !out) return BDEG_E_ARG;
   *out = b->stats;
+  return BDEG_OK;
+}
+
+int bdeg_batch_profile(bdeg_batch *b) {
+  if (!b) return BDEG_E_ARG;
+  if (b->dev.empty()) return BDEG_OK;
+  int st;
+  Device *D = device_get(&st);
+  if (!D) return st;
+  std::lock_guard<std::mutex> lk(D->mu);
+  b->job.shape.stats = true;
+  int rc = job_launch(b->job, D->stream);
+  b->job.shape.stats = false;
+  if (rc) return rc;
+  std::vector<SysAcc> acc;
+  DevCounters cnt{};
+  rc = job_collect(b->job, D->stream, acc, &cnt);
+  if (rc) return rc;
+  b->stats.ridges = cnt.ridges;
+  b->stats.inner_nodes = cnt.inner;
+  b->stats.spatial_updates = cnt.sp_upd;
+  b->stats.pruned = cnt.pruned;
+  b->stats.leaves = cnt.leaves;
+  b->stats.tiles = cnt.tiles;
   return BDEG_OK;
 }
 
@@ -388,11 +409,12 @@ int bdeg_nvol_points(const int32_t *points, const int64_t *heights, int32_t N, i
   job.pts.assign(points, points + (size_t)N * k);
   job.heights.assign(heights, heights + N);
   job.explicit_heights = true;
-  job.kmax = k;
+  job.kmin = job.kmax = k;
   uint64_t total = binom_u64(N, k + 1);
   uint64_t hi = std::min(rank_hi, total), lo = std::min(rank_lo, hi);
-  tiles_range(N, k, 0, lo, hi, choose_max_cost(hi - lo, default_waves(k, 4)), job.tiles);
-  std::stable_sort(job.tiles.begin(), job.tiles.end(), [](const Tile &a, const Tile &b) { return a.cost > b.cost; });
+  std::vector<TileC> tc;
+  tiles_range(N, k, 0, lo, hi, choose_max_cost(hi - lo, default_waves(k, k, 4)), tc);
+  tiles_sorted(tc, job.tiles);
   int rc = job_upload(job);
   if (rc) return rc;
   rc = job_launch(job, D->stream);
@@ -403,6 +425,19 @@ int bdeg_nvol_points(const int32_t *points, const int64_t *heights, int32_t N, i
   *nvol = bdeg_u128{acc[0].lo, acc[0].hi};
   *tie = (int32_t)acc[0].tie;
   if (cells) *cells = acc[0].cells;
+  return BDEG_OK;
+}
+
+int bdeg_plan_units(int32_t N, int32_t k, uint64_t rank_lo, uint64_t rank_hi, uint64_t max_cost,
+                    uint64_t *intervals, size_t cap, size_t *n_units) {
+  if (!n_units || k < 1 || k > BDEG_MAX_K || N < k + 1 || N > 64 || max_cost == 0) return BDEG_E_ARG;
+  std::vector<TileC> tc;
+  tiles_range(N, k, 0, rank_lo, rank_hi, max_cost, tc);
+  std::vector<Tile> tiles;
+  tiles_sorted(tc, tiles);
+  *n_units = tiles.size();
+  if (tiles.size() > cap) return BDEG_E_NOMEM;
+  for (size_t u = 0; u < tiles.size(); u++) tile_interval(tiles[u], k, &intervals[2 * u], &intervals[2 * u + 1]);
   return BDEG_OK;
 }
 

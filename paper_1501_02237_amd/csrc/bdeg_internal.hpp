@@ -25,14 +25,20 @@ struct SysDesc {
   uint64_t lift_key; // counter-based lifting key for the current attempt
 };
 
-// A work unit: the subtree of candidates that contain the prefix `mask` as
-// their top elements (colex), i.e. all (k+1)-subsets whose largest elements
-// are exactly the set bits of mask and whose remaining elements lie below the
-// lowest set bit.
+// A work unit: the candidates whose top elements (colex) are exactly the set
+// bits of `mask` and whose remaining elements lie below the lowest set bit,
+// with the next element restricted to [c_lo, c_hi] (a run of sibling
+// subtrees; 0 and 63 when unrestricted).
 struct Tile {
   uint64_t mask;
   uint32_t sys;
-  uint32_t cost; // subtree size estimate, saturated to 2^32-1
+  uint8_t c_lo, c_hi;
+  uint16_t pad;
+};
+// host-side work unit with its candidate count (for ordering)
+struct TileC {
+  Tile t;
+  uint64_t cost;
 };
 
 // Per-system device accumulators (sum of |det| of lower facets, as a 128-bit
@@ -46,10 +52,9 @@ struct SysAcc {
 
 // Device-wide counters (zeroed per run).
 struct DevCounters {
-  uint64_t nodes[BDEG_MAX_K]; // nodes created per depth
-  uint64_t pruned, leaves, tiles;
+  uint64_t ridges, inner, sp_upd, pruned, leaves, tiles;
   uint32_t next_tile; // dynamic work queue head
-  uint32_t pad;
+  uint32_t error;     // a work unit exceeded its step budget (watchdog)
 };
 
 // ------------------------------------------------------------ host algebra
@@ -71,10 +76,14 @@ bool device_bounds_ok(const int32_t *pts, int N, int k, uint64_t height_span);
 uint64_t binom_u64(int n, int r); // saturates at UINT64_MAX
 // Cover all (k+1)-subsets of N points with subtrees of at most `max_cost`
 // candidates where possible (never deeper than k points chosen).
-void tiles_full(int N, int k, uint32_t sys, uint64_t max_cost, std::vector<Tile> &out);
+void tiles_full(int N, int k, uint32_t sys, uint64_t max_cost, std::vector<TileC> &out);
 // Exactly the candidates with colex rank in [lo, hi).
 // Subtrees fully inside the range are further split down to max_cost.
-void tiles_range(int N, int k, uint32_t sys, uint64_t lo, uint64_t hi, uint64_t max_cost, std::vector<Tile> &out);
+void tiles_range(int N, int k, uint32_t sys, uint64_t lo, uint64_t hi, uint64_t max_cost, std::vector<TileC> &out);
+// colex rank interval [start, end) covered by a unit
+void tile_interval(const Tile &t, int k, uint64_t *start, uint64_t *end);
+// order work units by decreasing cost and strip the costs
+void tiles_sorted(std::vector<TileC> &in, std::vector<Tile> &out);
 
 // ------------------------------------------------------------ lifting
 uint64_t lift_key(uint64_t seed, uint32_t sys_index, uint32_t attempt);
@@ -83,15 +92,17 @@ uint64_t lift_key(uint64_t seed, uint32_t sys_index, uint32_t attempt);
 struct LaunchShape {
   int blocks = 0;
   int waves_per_block = 4;
+  bool stats = false; // run the variant that counts its work
 };
 // Launch helpers; all asynchronous on `stream` (a hipStream_t).
 int launch_lift(void *stream, const SysDesc *d_sys, const int32_t *d_active, int n_active,
                 int64_t *d_heights);
 int launch_clear(void *stream, SysAcc *d_acc, int n_sys, DevCounters *d_cnt);
+int launch_clear_list(void *stream, SysAcc *d_acc, const int32_t *d_list, int n);
 int launch_enumerate(void *stream, const SysDesc *d_sys, const int32_t *d_pts,
                      const int64_t *d_heights, const Tile *d_tiles, uint32_t n_tiles, SysAcc *d_acc,
-                     DevCounters *d_cnt, int kmax, LaunchShape shape);
+                     DevCounters *d_cnt, int kmin, int kmax, LaunchShape shape);
 int device_cu_count();
-int max_enum_blocks(int kmax, int waves_per_block); // occupancy-derived persistent grid
+int max_enum_blocks(int kmin, int kmax, int waves_per_block); // occupancy-derived persistent grid
 
 } // namespace bdeg

@@ -44,8 +44,8 @@ Device *device_get(int *status) {
   return &g_device;
 }
 
-int default_waves(int kmax, int waves_per_block) {
-  int blocks = max_enum_blocks(kmax, waves_per_block);
+int default_waves(int kmin, int kmax, int waves_per_block) {
+  int blocks = max_enum_blocks(kmin, kmax, waves_per_block);
   return blocks > 0 ? blocks * waves_per_block : 1024;
 }
 
@@ -67,9 +67,11 @@ void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t ma
   job.sys.clear();
   job.pts.clear();
   job.tiles.clear();
+  job.kmin = 1 << 30;
   job.kmax = 0;
   job.explicit_heights = false;
   int ht = 0;
+  std::vector<TileC> tc;
   for (size_t s = 0; s < systems.size(); s++) {
     const HostSys &h = systems[s];
     SysDesc d;
@@ -84,9 +86,11 @@ void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t ma
     job.pts.insert(job.pts.end(), h.pts.begin(), h.pts.end());
     ht += h.N;
     job.kmax = std::max(job.kmax, h.k);
-    tiles_full(h.N, h.k, (uint32_t)s, max_cost, job.tiles);
+    job.kmin = std::min(job.kmin, h.k);
+    tiles_full(h.N, h.k, (uint32_t)s, max_cost, tc);
   }
-  std::stable_sort(job.tiles.begin(), job.tiles.end(), [](const Tile &a, const Tile &b) { return a.cost > b.cost; });
+  if (job.kmin > job.kmax) job.kmin = job.kmax;
+  tiles_sorted(tc, job.tiles);
   job.heights.assign(ht, 0);
 }
 
@@ -136,7 +140,7 @@ int job_launch_pre(Job &job, hipStream_t stream) {
 
 int job_launch_enum(Job &job, hipStream_t stream) {
   return launch_enumerate(stream, job.d_sys, job.d_pts, job.d_hts, job.d_tiles, (uint32_t)job.tiles.size(),
-                          job.d_acc, job.d_cnt, job.kmax, job.shape);
+                          job.d_acc, job.d_cnt, job.kmin, job.kmax, job.shape);
 }
 
 int job_launch(Job &job, hipStream_t stream, hipEvent_t e0, hipEvent_t e1) {
@@ -150,12 +154,15 @@ int job_launch(Job &job, hipStream_t stream, hipEvent_t e0, hipEvent_t e1) {
 
 int job_collect(Job &job, hipStream_t stream, std::vector<SysAcc> &acc, DevCounters *cnt) {
   acc.resize(job.sys.size());
+  DevCounters local;
+  DevCounters *c = cnt ? cnt : &local;
   if (!acc.empty() &&
       hipMemcpyAsync(acc.data(), job.d_acc, acc.size() * sizeof(SysAcc), hipMemcpyDeviceToHost, stream) != hipSuccess)
     return BDEG_E_DEVICE;
-  if (cnt && hipMemcpyAsync(cnt, job.d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, stream) != hipSuccess)
+  if (hipMemcpyAsync(c, job.d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, stream) != hipSuccess)
     return BDEG_E_DEVICE;
   if (hipStreamSynchronize(stream) != hipSuccess) return BDEG_E_DEVICE;
+  if (c->error) return BDEG_E_DEVICE; // a work unit hit the watchdog
   return BDEG_OK;
 }
 

@@ -34,7 +34,7 @@ struct Job {
   std::vector<SysDesc> sys;
   std::vector<int32_t> pts;
   std::vector<Tile> tiles;
-  int kmax = 0;
+  int kmin = 0, kmax = 0;
   bool explicit_heights = false;
   std::vector<int64_t> heights; // when explicit
 
@@ -64,6 +64,6 @@ int job_launch(Job &job, hipStream_t stream, hipEvent_t ev_kernel_start = nullpt
 int job_collect(Job &job, hipStream_t stream, std::vector<SysAcc> &acc, DevCounters *cnt);
 
 uint64_t choose_max_cost(uint64_t total_candidates, int waves);
-int default_waves(int kmax, int waves_per_block);
+int default_waves(int kmin, int kmax, int waves_per_block);
 
 } // namespace bdeg

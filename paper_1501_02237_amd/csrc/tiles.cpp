@@ -8,6 +8,7 @@
 // unit, described by the bit mask of its prefix.
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "bdeg_internal.hpp"
@@ -25,31 +26,64 @@ uint64_t binom_u64(int n, int r) {
   return (uint64_t)c;
 }
 
-static inline uint32_t sat32(uint64_t x) { return x > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)x; }
+static void emit(std::vector<TileC> &out, uint32_t sys, uint64_t mask, int c_lo, int c_hi, uint64_t cost) {
+  TileC t;
+  t.t.mask = mask;
+  t.t.sys = sys;
+  t.t.c_lo = (uint8_t)c_lo;
+  t.t.c_hi = (uint8_t)c_hi;
+  t.t.pad = 0;
+  t.cost = cost;
+  out.push_back(t);
+}
 
 // prefix `mask` has L elements with lowest element e; its subtree has
-// C(e, k+1-L) candidates.  Split while larger than max_cost and fewer than k
-// points are fixed (a k-point prefix has at most e <= 63 leaves).
-static void split(int k, uint32_t sys, uint64_t mask, int L, int e, uint64_t max_cost,
-                  std::vector<Tile> &out) {
+// C(e, k+1-L) candidates.  A subtree above max_cost is split into its
+// children (next element c, C(c, k-L) candidates each); children at or below
+// max_cost are grouped into runs of consecutive siblings of total cost at
+// most max_cost, so that one work unit derives the shared prefix once.
+// A k-point prefix (a ridge, at most e <= 63 leaves) is never split.
+static void split(int k, uint32_t sys, uint64_t mask, int L, int e, uint64_t max_cost, std::vector<TileC> &out) {
   uint64_t cost = binom_u64(e, k + 1 - L);
   if (cost == 0) return;
   if (cost <= max_cost || L >= k) {
-    out.push_back(Tile{mask, sys, sat32(cost)});
+    emit(out, sys, mask, 0, 63, cost);
     return;
   }
-  for (int c = e - 1; c >= k - L; c--) split(k, sys, mask | (1ull << c), L + 1, c, max_cost, out);
+  int run_hi = -1, run_lo = -1;
+  uint64_t run_cost = 0;
+  auto flush = [&]() {
+    if (run_hi >= 0) emit(out, sys, mask, run_lo, run_hi, run_cost);
+    run_hi = run_lo = -1;
+    run_cost = 0;
+  };
+  for (int c = e - 1; c >= k - L; c--) {
+    uint64_t cc = binom_u64(c, k - L);
+    if (cc == 0) continue;
+    if (cc > max_cost) {
+      flush();
+      split(k, sys, mask | (1ull << c), L + 1, c, max_cost, out);
+      continue;
+    }
+    if (run_hi >= 0 && run_cost + cc > max_cost) flush();
+    if (run_hi < 0) run_hi = c;
+    run_lo = c;
+    run_cost += cc;
+  }
+  flush();
 }
 
-void tiles_full(int N, int k, uint32_t sys, uint64_t max_cost, std::vector<Tile> &out) {
+void tiles_full(int N, int k, uint32_t sys, uint64_t max_cost, std::vector<TileC> &out) {
   if (max_cost == 0) max_cost = 1;
+  // every work unit fixes at least the top element b (a kernel needs a base
+  // point), so the top elements are never grouped
   for (int b = N - 1; b >= k; b--) split(k, sys, 1ull << b, 1, b, max_cost, out);
 }
 
 // Ranks of the children of a node: the next element c (position i = k - L)
 // covers [base + C(c, i+1), base + C(c+1, i+1)).
-static void cover(int k, uint32_t sys, uint64_t mask, int L, int e, uint64_t base, uint64_t lo,
-                  uint64_t hi, uint64_t max_cost, std::vector<Tile> &out) {
+static void cover(int k, uint32_t sys, uint64_t mask, int L, int e, uint64_t base, uint64_t lo, uint64_t hi,
+                  uint64_t max_cost, std::vector<TileC> &out) {
   const int i = k - L;
   for (int c = i; c < e; c++) {
     uint64_t start = base + binom_u64(c, i + 1);
@@ -64,13 +98,40 @@ static void cover(int k, uint32_t sys, uint64_t mask, int L, int e, uint64_t bas
   }
 }
 
-void tiles_range(int N, int k, uint32_t sys, uint64_t lo, uint64_t hi, uint64_t max_cost,
-                 std::vector<Tile> &out) {
+void tiles_range(int N, int k, uint32_t sys, uint64_t lo, uint64_t hi, uint64_t max_cost, std::vector<TileC> &out) {
   uint64_t total = binom_u64(N, k + 1);
   if (hi > total) hi = total;
   if (lo >= hi) return;
   if (max_cost == 0) max_cost = 1;
   cover(k, sys, 0, 0, N, 0, lo, hi, max_cost, out);
+}
+
+// colex rank interval of a work unit
+void tile_interval(const Tile &t, int k, uint64_t *start, uint64_t *end) {
+  uint64_t base = 0, m = t.mask;
+  int L = 0, e = 64;
+  while (m) {
+    const int c = 63 - __builtin_clzll(m);
+    base += binom_u64(c, k + 1 - L); // element at colex position k - L
+    m &= ~(1ull << c);
+    e = c;
+    L++;
+  }
+  const int i = k - L; // position of the next element
+  if (L == k + 1) {
+    *start = base;
+    *end = base + 1;
+    return;
+  }
+  int hi = std::min(e - 1, (int)t.c_hi), lo = std::max(i, (int)t.c_lo);
+  *start = base + binom_u64(lo, i + 1);
+  *end = base + binom_u64(hi + 1, i + 1);
+}
+
+void tiles_sorted(std::vector<TileC> &in, std::vector<Tile> &out) {
+  std::stable_sort(in.begin(), in.end(), [](const TileC &a, const TileC &b) { return a.cost > b.cost; });
+  out.resize(in.size());
+  for (size_t i = 0; i < in.size(); i++) out[i] = in[i].t;
 }
 
 // Counter-based lifting key: SplitMix64's finaliser (Steele, Lea, Flood 2014)

@@ -30,9 +30,11 @@ def say(*a):
 
 @pytest.fixture(scope="module", autouse=True)
 def _device():
+    say("gpu fixture: importing torch")
     import torch
 
     assert torch.cuda.is_available(), "gpu tests need a GPU"
+    say("gpu fixture: torch ready")
     oracle.build(force=False)
     bd.lib()
 
@@ -231,7 +233,11 @@ def test_prepared_batch_graph_replays():
             res = b.results()
             assert [_gres(r) for r in res] == expect
             st = b.stats()
-            assert st["kernel_ms"] > 0 and st["tiles"] > 0
+            assert st["kernel_ms"] > 0
+        st = b.profile()
+        assert st["tiles"] > 0 and st["leaves"] > 0
+        b.run()  # the profiling pass leaves the captured pass intact
+        assert [_gres(r) for r in b.results()] == expect
     finally:
         b.close()
 
@@ -281,3 +287,49 @@ def test_cfg3_batch_4096():
     for e, r in zip(exp, res):
         assert r["status"] == 0
         assert (r["k"], r["comps"], r["nvol"]) == (e["k"], e["comps"], e["nvol"]), e["index"]
+
+
+# ------------------------------------------------------------------ serving
+def test_serving_mix_equals_alone():
+    """Requests submitted together (they share device steps) give exactly the
+    results of solving each one alone; the small ones also match the oracle."""
+    rng = gen.stream(0x5EED0401, 0, gen.PURPOSE_SIZES)
+    mats = []
+    for i in range(40):
+        n = rng.uniform_int(8, 24)
+        k = rng.uniform_int(1, 7)
+        mats.append(gen.quiver_matrix(0x5EED0401, i, n, n - k, 2, 3))
+    mats.append(np.zeros((1, 6), dtype=np.int64))          # k = n
+    mats.append(np.array([[1, 1], [0, 1]], dtype=np.int64))  # k = 0
+    alone = [bd.degree(A, seed=17, lift_bits=20) for A in mats]
+    srv = bd.Server(64 << 20)
+    try:
+        tickets = [srv.submit(A, seed=17, lift_bits=20) for A in mats]
+        say("serving: submitted", len(tickets))
+        got = [srv.wait(t) for t in tickets]
+        lat = [srv.latency_ms(t) for t in tickets]
+    finally:
+        srv.close()
+    for A, a, g in zip(mats, alone, got):
+        assert g["status"] == 0
+        assert (g["k"], g["comps"], g["nvol"], g["attempts"], g["cells"]) == \
+            (a["k"], a["comps"], a["nvol"], a["attempts"], a["cells"])
+    for A, g in zip(mats[:12], got[:12]):
+        assert _gres(g) == _ores(A)
+    assert all(x is not None and x >= 0 for x in lat)
+
+
+def test_serving_small_budget_and_ties():
+    """A budget of a few slots forces admission to wait; 4-bit heights force
+    tie redraws inside the engine; results still equal the one-shot path."""
+    mats = [gen.quiver_matrix(0x5EED0402, i, 14, 9, 2, 3) for i in range(12)]
+    alone = [bd.degree(A, seed=5, lift_bits=4, check=False) for A in mats]
+    srv = bd.Server(3 * 4096 + 2048)
+    try:
+        tickets = [srv.submit(A, seed=5, lift_bits=4) for A in mats]
+        got = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    for a, g in zip(alone, got):
+        assert (g["status"], g["nvol"], g["attempts"]) == (a["status"], a["nvol"], a["attempts"])
+    assert any(g["attempts"] > 1 for g in got)

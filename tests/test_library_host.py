@@ -113,3 +113,32 @@ def test_degree_k0_needs_no_device():
     # k = 0 is answered on the host (a finite set of points, nvol = 1)
     r = bd.degree(np.array([[2, 1], [1, 1]], dtype=np.int64), check=False)
     assert (r["status"], r["k"], r["comps"], r["nvol"]) == (0, 0, 1, 1)
+
+
+@pytest.mark.parametrize("N,k,cap", [(13, 6, 256), (29, 8, 1000), (29, 8, 5000), (37, 10, 200000), (64, 3, 1000),
+                                     (20, 1, 256), (17, 12, 256), (40, 5, 777), (64, 12, 1 << 40)])
+def test_work_units_cover_every_candidate_once(N, k, cap):
+    """Units of the full candidate space tile [0, C(N, k+1)) exactly."""
+    iv = bd.plan_units(N, k, 0, None, cap)
+    total = math.comb(N, k + 1)
+    order = np.argsort(iv[:, 0], kind="stable")
+    s, e = iv[order, 0].astype(object), iv[order, 1].astype(object)
+    assert s[0] == 0 and e[-1] == total
+    assert all(e[i] == s[i + 1] for i in range(len(s) - 1))
+    assert all(e[i] > s[i] for i in range(len(s)))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_work_units_cover_rank_ranges(seed):
+    rng = gen.stream(0x5EED0103, seed, gen.PURPOSE_MATRIX)
+    N = rng.uniform_int(6, 64)
+    k = rng.uniform_int(1, min(12, N - 1))
+    total = math.comb(N, k + 1)
+    lo = rng.next() % total
+    hi = lo + 1 + rng.next() % (total - lo)
+    cap = max((hi - lo) // 20000, 1) + rng.next() % 5000
+    iv = bd.plan_units(N, k, lo, hi, cap)
+    order = np.argsort(iv[:, 0], kind="stable")
+    s, e = iv[order, 0].astype(object), iv[order, 1].astype(object)
+    assert s[0] == lo and e[-1] == hi
+    assert all(e[i] == s[i + 1] for i in range(len(s) - 1))
