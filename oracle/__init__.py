@@ -18,6 +18,10 @@ What it computes, plainly and exactly (paper Sections 2 and 4):
     - k = 0: nvol = 1 (a finite set of points, each of degree 1).
 * ``oracle_nvol_points(points, heights)`` -> the same volume sum for a caller's
   point set and explicit heights, optionally over a colex rank range.
+* ``cells_range(points, heights)`` -> the lower facets themselves (the cells of
+  the regular subdivision) with their inner normals (alpha, 1), alpha exact
+  rationals num / den (eq. ``lower-d-face-again``; the start data of the
+  polyhedral homotopy of Section 6).
 
 Parity unpinned: nothing.  Every function is pinned by the tests in
 ``tests/test_oracle_*.py`` against closed forms, brute-force lattice-point
@@ -79,6 +83,12 @@ def _load():
             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
         ]
         lib.oracle_nvol_range.restype = ctypes.c_int
+        lib.oracle_cells_range.argtypes = [
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+            ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int),
+        ]
+        lib.oracle_cells_range.restype = ctypes.c_int
         lib.oracle_binom.argtypes = [ctypes.c_int, ctypes.c_int]
         lib.oracle_binom.restype = ctypes.c_uint64
         _lib = lib
@@ -124,6 +134,47 @@ def nvol_range(points, heights, rank_lo: int = 0, rank_hi: int | None = None, th
     if v >= 1 << 127:
         v -= 1 << 128
     return VolumePart(v, bool(tie.value), cells.value, dz.value)
+
+
+@dataclass
+class Cells:
+    masks: np.ndarray  # uint64 [c]: bit i set for vertex i
+    num: np.ndarray    # int64 [c, k]: inner normal numerators
+    den: np.ndarray    # uint64 [c]: denominators = normalized volumes |D|
+    tie: bool
+
+    def as_set(self) -> set:
+        return {(int(m), tuple(int(x) for x in n), int(d)) for m, n, d in zip(self.masks, self.num, self.den)}
+
+
+def cells_range(points, heights, rank_lo: int = 0, rank_hi: int | None = None,
+                threads: int | None = None, cap: int = 1024) -> Cells:
+    """The lower facets (cells of the regular subdivision) among candidates
+    with colex rank in [rank_lo, rank_hi), each with its inner normal
+    (alpha, 1), alpha = num / den (eq. ``lower-d-face-again``)."""
+    P = np.ascontiguousarray(np.asarray(points, dtype=np.int64))
+    H = np.ascontiguousarray(np.asarray(heights, dtype=np.int64))
+    N, k = P.shape
+    if H.shape != (N,):
+        raise OracleError("one height per point")
+    rh = MASK64 if rank_hi is None else int(rank_hi)
+    while True:
+        masks = np.zeros(cap, dtype=np.uint64)
+        num = np.zeros((cap, k), dtype=np.int64)
+        den = np.zeros(cap, dtype=np.uint64)
+        cnt, tie = ctypes.c_uint64(), ctypes.c_int()
+        rc = _load().oracle_cells_range(
+            P.ctypes.data, H.ctypes.data, N, k, int(rank_lo), rh, threads or default_threads(), cap,
+            masks.ctypes.data, num.ctypes.data, den.ctypes.data, ctypes.byref(cnt), ctypes.byref(tie),
+        )
+        if rc == ORACLE_E_OVERFLOW:
+            raise OracleError("overflow in the oracle cell list")
+        if rc != ORACLE_OK:
+            raise OracleError(f"oracle_cells_range: bad arguments (N={N}, k={k})")
+        if cnt.value <= cap:
+            c = cnt.value
+            return Cells(masks[:c].copy(), num[:c].copy(), den[:c].copy(), bool(tie.value))
+        cap = int(cnt.value)
 
 
 def oracle_heights(seed: int, attempt: int, N: int, bits: int) -> np.ndarray:

@@ -21,6 +21,12 @@
  *   all s_j > 0 -> lower facet: add |D|
  *   no s_j < 0 but some s_j == 0 -> the lifting is not generic (a "tie")
  *
+ * A lower facet's inner normal is (alpha, 1) with alpha_i = n_i / n_k (the
+ * unique vector of eq. ``lower-d-face-again``): the linear functional
+ * <., (alpha, 1)> is equal on the facet's lifted vertices and strictly larger
+ * on every other lifted point.  oracle_cells_range lists the facets with the
+ * numerators n_0..n_{k-1} and the denominator n_k = |D|.
+ *
  * Determinants use Bareiss fraction-free elimination with row pivoting.
  * Every product, sum and difference is overflow-checked in __int128; an
  * overflow aborts the computation with ORACLE_E_OVERFLOW rather than return
@@ -59,6 +65,12 @@ typedef struct {
   uint64_t lo, hi, chunk;
   uint64_t next; /* shared chunk counter (atomic) */
   int err;       /* shared error flag (atomic) */
+  /* optional cell list: facets beyond cap are counted, not stored */
+  uint64_t cap;
+  uint64_t *masks;
+  int64_t *num; /* cap x k */
+  uint64_t *den;
+  uint64_t n_emit; /* shared (atomic) */
 } job_t;
 
 typedef struct {
@@ -163,6 +175,18 @@ static int test_candidate(const job_t *J, const int *c, worker_t *w) {
   if (zero) { w->tie = 1; return 0; }
   if (add_ck(w->vol, nrm[k], &w->vol)) return 1;
   w->cells++;
+  if (J->masks) {
+    for (int q = 0; q < d; q++)
+      if (nrm[q] > INT64_MAX || nrm[q] < INT64_MIN) return 1;
+    const uint64_t idx = __atomic_fetch_add((uint64_t *)&J->n_emit, 1, __ATOMIC_RELAXED);
+    if (idx < J->cap) {
+      uint64_t m = 0;
+      for (int i = 0; i <= k; i++) m |= 1ull << c[i];
+      J->masks[idx] = m;
+      for (int q = 0; q < k; q++) J->num[idx * (uint64_t)k + q] = (int64_t)nrm[q];
+      J->den[idx] = (uint64_t)nrm[k];
+    }
+  }
   return 0;
 }
 
@@ -196,16 +220,15 @@ static void *worker_main(void *arg) {
  *   out_tie: 1 if a non-generic lower face was seen.
  * Returns ORACLE_OK, ORACLE_E_ARG or ORACLE_E_OVERFLOW.
  */
-int oracle_nvol_range(const int64_t *pts, const int64_t *hts, int N, int k, uint64_t rank_lo,
-                      uint64_t rank_hi, int nthreads, uint64_t *out_vol_lo, uint64_t *out_vol_hi,
-                      int *out_tie, uint64_t *out_cells, uint64_t *out_dzero) {
+static int run_range(job_t *JP, const int64_t *pts, const int64_t *hts, int N, int k, uint64_t rank_lo,
+                     uint64_t rank_hi, int nthreads, uint64_t *out_vol_lo, uint64_t *out_vol_hi, int *out_tie,
+                     uint64_t *out_cells, uint64_t *out_dzero) {
   if (!pts || !hts || k < 1 || k >= ORACLE_MAXK || N > ORACLE_MAXN || N < k + 1 || nthreads < 1)
     return ORACLE_E_ARG;
   uint64_t total = oracle_binom(N, k + 1);
   if (rank_hi > total) rank_hi = total;
   if (rank_lo > rank_hi) rank_lo = rank_hi;
-  job_t J;
-  memset(&J, 0, sizeof J);
+  job_t J = *JP;
   J.pts = pts; J.hts = hts; J.N = N; J.k = k;
   J.lo = rank_lo; J.hi = rank_hi; J.next = rank_lo;
   uint64_t span = rank_hi - rank_lo;
@@ -229,6 +252,7 @@ int oracle_nvol_range(const int64_t *pts, const int64_t *hts, int N, int k, uint
   }
   free(ws);
   free(th);
+  JP->n_emit = J.n_emit;
   if (err) return ORACLE_E_OVERFLOW;
   *out_vol_lo = (uint64_t)vol;
   *out_vol_hi = (uint64_t)(vol >> 64);
@@ -236,4 +260,37 @@ int oracle_nvol_range(const int64_t *pts, const int64_t *hts, int N, int k, uint
   if (out_cells) *out_cells = cells;
   if (out_dzero) *out_dzero = dzero;
   return ORACLE_OK;
+}
+
+int oracle_nvol_range(const int64_t *pts, const int64_t *hts, int N, int k, uint64_t rank_lo,
+                      uint64_t rank_hi, int nthreads, uint64_t *out_vol_lo, uint64_t *out_vol_hi,
+                      int *out_tie, uint64_t *out_cells, uint64_t *out_dzero) {
+  job_t J;
+  memset(&J, 0, sizeof J);
+  return run_range(&J, pts, hts, N, k, rank_lo, rank_hi, nthreads, out_vol_lo, out_vol_hi, out_tie, out_cells,
+                   out_dzero);
+}
+
+/*
+ * The lower facets among the candidates with colex rank in [rank_lo, rank_hi):
+ * vertex masks (bit i = point i) and inner normals alpha = num / den (num:
+ * k entries per facet, den = the facet's normalized volume |D| > 0), in no
+ * particular order.  At most cap facets are stored; *out_count is the number
+ * found (a count above cap asks for a larger buffer).  *out_tie as for the
+ * volume.  A numerator outside int64 returns ORACLE_E_OVERFLOW.
+ */
+int oracle_cells_range(const int64_t *pts, const int64_t *hts, int N, int k, uint64_t rank_lo, uint64_t rank_hi,
+                       int nthreads, uint64_t cap, uint64_t *masks, int64_t *num, uint64_t *den,
+                       uint64_t *out_count, int *out_tie) {
+  if (!masks || !num || !den || !out_count || !out_tie) return ORACLE_E_ARG;
+  job_t J;
+  memset(&J, 0, sizeof J);
+  J.cap = cap;
+  J.masks = masks;
+  J.num = num;
+  J.den = den;
+  uint64_t lo, hi;
+  int rc = run_range(&J, pts, hts, N, k, rank_lo, rank_hi, nthreads, &lo, &hi, out_tie, 0, 0);
+  *out_count = J.n_emit;
+  return rc;
 }
