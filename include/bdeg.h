@@ -155,6 +155,43 @@ int bdeg_nvol_points(const int32_t *points, const int64_t *heights, int32_t N, i
                      uint64_t *cells);
 
 /*
+ * Cells of the regular subdivision (Section 4) with their inner normals:
+ * the lower facets among the candidates whose colex rank lies in
+ * [rank_lo, rank_hi), each with the unique inner normal (alpha, 1) of eq.
+ * "lower-d-face-again", alpha = num / den exactly.  They are the start data
+ * of the polyhedral homotopies of Section 5 (one homotopy per cell).
+ *   points, heights, N, k, rank_lo, rank_hi  as for bdeg_nvol_points;
+ *   cell_masks [cap]      bit i set for vertex i (the facet's k+1 points);
+ *   normal_num [cap * k]  numerators of alpha, one row of k per cell;
+ *   normal_den [cap]      den = the cell's normalized volume |D| > 0;
+ *   *n_cells              the number of cells found; at most cap are written
+ *                         (a larger count asks for a larger buffer; cap = 0
+ *                         only counts, and the arrays may then be NULL);
+ *   *tie                  as for bdeg_nvol_points (the list is then not a
+ *                         subdivision).
+ * Cells come in no particular order; den over all cells sums to the volume
+ * bdeg_nvol_points gives.  Device memory for cap cells is allocated per call.
+ * Errors: BDEG_E_ARG, BDEG_E_OVERFLOW (device bound, or a numerator outside
+ * int64), BDEG_E_DEVICE, BDEG_E_NOMEM.
+ */
+int bdeg_cells_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k,
+                      uint64_t rank_lo, uint64_t rank_hi, uint64_t cap, uint64_t *cell_masks,
+                      int64_t *normal_num, uint64_t *normal_den, uint64_t *n_cells, int32_t *tie);
+
+/*
+ * The regular subdivision behind bdeg_degree: the same host prologue, seeded
+ * lifting and tie retries, so *out equals bdeg_degree(A, m, n, seed,
+ * lift_bits) and the cells' den sum to out->nvol.  Also returned: the point
+ * set (points: room for (n+1)*n int32; (n+1)*k written, point 0 first), the
+ * heights of the lifting that succeeded (heights: n+1 int64) and the cells
+ * as for bdeg_cells_points (normal_num: room for cap*n int64; cap*k written).
+ * k == 0 or an error: *n_cells = 0 and the status as for bdeg_degree.
+ */
+int bdeg_subdivision(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int32_t lift_bits,
+                     uint64_t cap, int32_t *points, int64_t *heights, uint64_t *cell_masks,
+                     int64_t *normal_num, uint64_t *normal_den, uint64_t *n_cells, bdeg_result *out);
+
+/*
  * Host prologue only (no device): rank, k, components and the point set
  * {0, v_1..v_n} the device would use (Euclid column elimination with a
  * pairwise-reduced saturated kernel basis).  points must hold (n+1)*n int32;

@@ -21,7 +21,7 @@ What it computes, plainly and exactly (paper Sections 2 and 4):
 * ``cells_range(points, heights)`` -> the lower facets themselves (the cells of
   the regular subdivision) with their inner normals (alpha, 1), alpha exact
   rationals num / den (eq. ``lower-d-face-again``; the start data of the
-  polyhedral homotopy of Section 6).
+  polyhedral homotopy of Section 5).
 
 Parity unpinned: nothing.  Every function is pinned by the tests in
 ``tests/test_oracle_*.py`` against closed forms, brute-force lattice-point

@@ -93,6 +93,8 @@ def lib() -> ctypes.CDLL:
         "bdeg_batch_destroy": ([P], ctypes.c_int),
         "bdeg_nvol_points": ([P, P, I32, I32, U64, U64, P, P, P], ctypes.c_int),
         "bdeg_kernel_points": ([P, I32, I32, P, P, P, P], ctypes.c_int),
+        "bdeg_cells_points": ([P, P, I32, I32, U64, U64, U64, P, P, P, P, P], ctypes.c_int),
+        "bdeg_subdivision": ([P, I32, I32, U64, I32, U64, P, P, P, P, P, P, P], ctypes.c_int),
         "bdeg_serve_open": ([SZ, P], ctypes.c_int),
         "bdeg_serve_submit": ([P, P, I32, I32, U64, I32, P], ctypes.c_int),
         "bdeg_serve_poll": ([P, U64, P], ctypes.c_int),
@@ -200,6 +202,72 @@ def nvol_points(points, heights, rank_lo: int = 0, rank_hi: int | None = None) -
     if rc != BDEG_OK:
         raise BdegError(rc, "bdeg_nvol_points")
     return VolumeRange(nv.value, bool(tie.value), cells.value)
+
+
+@dataclass
+class Cells:
+    """Lower facets with inner normals (alpha, 1), alpha = num / den."""
+    masks: np.ndarray  # uint64 [c]: bit i set for vertex i
+    num: np.ndarray    # int64 [c, k]
+    den: np.ndarray    # uint64 [c]: the cells' normalized volumes
+    tie: bool
+
+    def as_set(self) -> set:
+        return {(int(m), tuple(int(x) for x in n), int(d)) for m, n, d in zip(self.masks, self.num, self.den)}
+
+
+def _cell_arrays(cap: int, k: int):
+    return (np.zeros(max(cap, 1), dtype=np.uint64), np.zeros((max(cap, 1), max(k, 1)), dtype=np.int64),
+            np.zeros(max(cap, 1), dtype=np.uint64))
+
+
+def cells_points(points, heights, rank_lo: int = 0, rank_hi: int | None = None, cap: int = 65536) -> Cells:
+    """Cells of the regular subdivision among candidates of colex rank in
+    [rank_lo, rank_hi), with exact inner normals (a second call with a larger
+    buffer when more than cap cells exist)."""
+    P = np.ascontiguousarray(np.asarray(points, dtype=np.int32))
+    H = np.ascontiguousarray(np.asarray(heights, dtype=np.int64))
+    N, k = P.shape
+    hi = U64_MAX if rank_hi is None else rank_hi
+    while True:
+        masks, num, den = _cell_arrays(cap, k)
+        cnt, tie = ctypes.c_uint64(), ctypes.c_int32()
+        rc = lib().bdeg_cells_points(P.ctypes.data, H.ctypes.data, N, k, rank_lo, hi, cap, masks.ctypes.data,
+                                     num.ctypes.data, den.ctypes.data, ctypes.byref(cnt), ctypes.byref(tie))
+        if rc != BDEG_OK:
+            raise BdegError(rc, "bdeg_cells_points")
+        c = cnt.value
+        if c <= cap:
+            return Cells(masks[:c].copy(), num[:c, :k].copy(), den[:c].copy(), bool(tie.value))
+        cap = c
+
+
+def subdivision(A, seed: int = 1, lift_bits: int = 20, cap: int = 65536) -> dict:
+    """The regular subdivision behind degree(A, seed, lift_bits): the degree
+    result plus "points", "heights" (the lifting used) and "cell_list"."""
+    A = _mat(A)
+    m, n = A.shape
+    while True:
+        pts = np.zeros((n + 1) * n, dtype=np.int32)
+        hts = np.zeros(n + 1, dtype=np.int64)
+        masks, num_full, den = np.zeros(max(cap, 1), dtype=np.uint64), np.zeros(max(cap, 1) * n, dtype=np.int64), \
+            np.zeros(max(cap, 1), dtype=np.uint64)
+        cnt, r = ctypes.c_uint64(), Result()
+        rc = lib().bdeg_subdivision(A.ctypes.data, m, n, seed & U64_MAX, lift_bits, cap, pts.ctypes.data,
+                                    hts.ctypes.data, masks.ctypes.data, num_full.ctypes.data, den.ctypes.data,
+                                    ctypes.byref(cnt), ctypes.byref(r))
+        if rc != BDEG_OK:
+            raise BdegError(rc, "bdeg_subdivision")
+        c = cnt.value
+        if c <= cap:
+            break
+        cap = c
+    d = r.as_dict()
+    k = d["k"]
+    d["points"] = pts[: (n + 1) * k].reshape(n + 1, k)
+    d["heights"] = hts
+    d["cell_list"] = Cells(masks[:c].copy(), num_full[: c * k].reshape(c, k).copy(), den[:c].copy(), False)
+    return d
 
 
 class Batch:

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbdeg.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["algebra.cpp", "tiles.cpp", "runtime.cpp", "api.cpp", "serve.cpp", "kernels.hip"]
+SOURCES = ["algebra.cpp", "tiles.cpp", "runtime.cpp", "api.cpp", "serve.cpp", "kernels.hip",
+           "kernels_mixed12.hip", "kernels_mixed7.hip", "kernels_cells.hip"] + [f"kernels_k{k}.hip" for k in range(12, 0, -1)]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -24,8 +25,6 @@ ARCH = "gfx950"
 def _flags(src: str) -> list[str]:
     f = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]
     f += [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-    if not src.endswith(".hip"):
-        f += ["-x", "hip"] if False else []
     return f
 
 
@@ -33,7 +32,10 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs, procs = [], []
     t0 = time.time()
+    jobs = jobs or max(1, min(16, os.cpu_count() or 1))
     for s in SOURCES:
+        while sum(p.poll() is None for _, p in procs) >= jobs:
+            time.sleep(0.05)
         src = os.path.join(CSRC, s)
         obj = os.path.join(BUILD, s + ".o")
         cmd = [HIPCC, *_flags(s), "-c", src, "-o", obj]

@@ -144,6 +144,110 @@ int finish_device(Device *D, std::vector<HostSys> &dev, std::vector<bdeg_result>
   return BDEG_OK;
 }
 
+// Arguments of the point-set entry points: shape, |h| < 2^40, device bound.
+static int check_points(const int32_t *points, const int64_t *heights, int N, int k) {
+  if (!points || !heights || k < 1 || k > BDEG_MAX_K || N < k + 1 || N > 64) return BDEG_E_ARG;
+  int64_t hmin = heights[0], hmax = heights[0];
+  for (int j = 0; j < N; j++) {
+    if (heights[j] >= (1ll << 40) || heights[j] <= -(1ll << 40)) return BDEG_E_ARG;
+    hmin = std::min(hmin, heights[j]);
+    hmax = std::max(hmax, heights[j]);
+  }
+  if (!device_bounds_ok(points, N, k, (uint64_t)(hmax - hmin))) return BDEG_E_OVERFLOW;
+  return BDEG_OK;
+}
+
+// One caller point set with explicit heights, candidates of colex rank in [rank_lo, rank_hi).
+static void points_job(Job &job, const int32_t *points, const int64_t *heights, int N, int k, uint64_t rank_lo,
+                       uint64_t rank_hi) {
+  job.sys.clear();
+  job.tiles.clear();
+  SysDesc d;
+  d.N = N;
+  d.k = k;
+  d.pt_off = 0;
+  d.ht_off = 0;
+  d.lift_bits = 0;
+  d.npad_log2 = npad_log2_for(N);
+  d.lift_key = 0;
+  job.sys.push_back(d);
+  job.pts.assign(points, points + (size_t)N * k);
+  job.heights.assign(heights, heights + N);
+  job.explicit_heights = true;
+  job.kmin = job.kmax = k;
+  const uint64_t total = binom_u64(N, k + 1);
+  const uint64_t hi = std::min(rank_hi, total), lo = std::min(rank_lo, hi);
+  std::vector<TileC> tc;
+  tiles_range(N, k, 0, lo, hi, choose_max_cost(hi - lo, default_waves(k, k, 4)), tc);
+  job_order_units(job, tc);
+}
+
+// Device buffers of one cell listing, freed on scope exit.
+struct CellBuffers {
+  uint64_t *masks = nullptr, *den = nullptr, *count = nullptr;
+  int64_t *num = nullptr;
+  uint32_t *err = nullptr;
+  int alloc(uint64_t cap, int k) {
+    if (cap > (1ull << 40) / (8ull * (k + 2))) return BDEG_E_NOMEM;
+    if (hipMalloc((void **)&count, sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc((void **)&err, sizeof(uint32_t)) != hipSuccess)
+      return BDEG_E_NOMEM;
+    if (cap > 0 && (hipMalloc((void **)&masks, cap * sizeof(uint64_t)) != hipSuccess ||
+                    hipMalloc((void **)&den, cap * sizeof(uint64_t)) != hipSuccess ||
+                    hipMalloc((void **)&num, cap * (size_t)k * sizeof(int64_t)) != hipSuccess))
+      return BDEG_E_NOMEM;
+    return BDEG_OK;
+  }
+  ~CellBuffers() {
+    for (void *p : {(void *)masks, (void *)den, (void *)count, (void *)num, (void *)err})
+      if (p) (void)hipFree(p);
+  }
+};
+
+// Enumerate an uploaded one-system job with the cell-listing kernel variant,
+// then compute the inner normals of the stored cells; copies out at most cap
+// cells, *n_cells = all found, *acc_out = the system's accumulator.
+static int list_cells(Device *D, Job &job, int N, int k, uint64_t cap, uint64_t *masks, int64_t *num,
+                      uint64_t *den, uint64_t *n_cells, SysAcc *acc_out) {
+  CellBuffers b;
+  int rc = b.alloc(cap, k);
+  if (rc) return rc;
+  if (hipMemsetAsync(b.count, 0, sizeof(uint64_t), D->stream) != hipSuccess ||
+      hipMemsetAsync(b.err, 0, sizeof(uint32_t), D->stream) != hipSuccess)
+    return BDEG_E_DEVICE;
+  job.shape.mode = MODE_EMIT;
+  job.shape.sink = CellSink{b.masks, cap, b.count};
+  rc = job_launch(job, D->stream);
+  job.shape.mode = MODE_PLAIN;
+  job.shape.sink = CellSink{nullptr, 0, nullptr};
+  if (rc) return rc;
+  std::vector<SysAcc> acc;
+  rc = job_collect(job, D->stream, acc, nullptr);
+  if (rc) return rc;
+  uint64_t count = 0;
+  if (hipMemcpyAsync(&count, b.count, sizeof count, hipMemcpyDeviceToHost, D->stream) != hipSuccess ||
+      hipStreamSynchronize(D->stream) != hipSuccess)
+    return BDEG_E_DEVICE;
+  if (count != acc[0].cells) return BDEG_E_DEVICE; // every accepted facet is listed exactly once
+  const uint64_t stored = std::min(count, cap);
+  rc = launch_cell_normals(D->stream, b.masks, stored, job.d_pts, job.d_hts, N, k, b.num, b.den, b.err);
+  if (rc) return rc;
+  uint32_t err = 0;
+  if (hipMemcpyAsync(&err, b.err, sizeof err, hipMemcpyDeviceToHost, D->stream) != hipSuccess) return BDEG_E_DEVICE;
+  if (stored > 0 &&
+      (hipMemcpyAsync(masks, b.masks, stored * sizeof(uint64_t), hipMemcpyDeviceToHost, D->stream) != hipSuccess ||
+       hipMemcpyAsync(num, b.num, stored * (size_t)k * sizeof(int64_t), hipMemcpyDeviceToHost, D->stream) !=
+           hipSuccess ||
+       hipMemcpyAsync(den, b.den, stored * sizeof(uint64_t), hipMemcpyDeviceToHost, D->stream) != hipSuccess))
+    return BDEG_E_DEVICE;
+  if (hipStreamSynchronize(D->stream) != hipSuccess) return BDEG_E_DEVICE;
+  if (err & 1u) return BDEG_E_DEVICE;   // a listed mask is not a (k+1)-subset
+  if (err & 2u) return BDEG_E_OVERFLOW; // a value outside the certified widths
+  *n_cells = count;
+  *acc_out = acc[0];
+  return BDEG_OK;
+}
+
 static int first_error(const std::vector<bdeg_result> &res) {
   for (auto &r : res)
     if (r.status != BDEG_OK) return r.status;
@@ -342,9 +446,9 @@ int bdeg_batch_profile(bdeg_batch *b) {
   Device *D = device_get(&st);
   if (!D) return st;
   std::lock_guard<std::mutex> lk(D->mu);
-  b->job.shape.stats = true;
+  b->job.shape.mode = MODE_STATS;
   int rc = job_launch(b->job, D->stream);
-  b->job.shape.stats = false;
+  b->job.shape.mode = MODE_PLAIN;
   if (rc) return rc;
   std::vector<SysAcc> acc;
   DevCounters cnt{};
@@ -382,40 +486,16 @@ int bdeg_batch_destroy(bdeg_batch *b) {
 
 int bdeg_nvol_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, uint64_t rank_lo,
                      uint64_t rank_hi, bdeg_u128 *nvol, int32_t *tie, uint64_t *cells) {
-  if (!points || !heights || !nvol || !tie || k < 1 || k > BDEG_MAX_K || N < k + 1 || N > 64) return BDEG_E_ARG;
-  int64_t hmin = heights[0], hmax = heights[0];
-  for (int j = 0; j < N; j++) {
-    if (heights[j] >= (1ll << 40) || heights[j] <= -(1ll << 40)) return BDEG_E_ARG;
-    hmin = std::min(hmin, heights[j]);
-    hmax = std::max(hmax, heights[j]);
-  }
-  if (!device_bounds_ok(points, N, k, (uint64_t)(hmax - hmin))) return BDEG_E_OVERFLOW;
+  if (!nvol || !tie) return BDEG_E_ARG;
+  int rc = check_points(points, heights, N, k);
+  if (rc) return rc;
   int st;
   Device *D = device_get(&st);
   if (!D) return st;
   std::lock_guard<std::mutex> lk(D->mu);
   static Job job; // scratch job reused across calls (guarded by the device mutex)
-  job.sys.clear();
-  job.tiles.clear();
-  SysDesc d;
-  d.N = N;
-  d.k = k;
-  d.pt_off = 0;
-  d.ht_off = 0;
-  d.lift_bits = 0;
-  d.npad_log2 = N <= 8 ? 3 : N <= 16 ? 4 : N <= 32 ? 5 : 6;
-  d.lift_key = 0;
-  job.sys.push_back(d);
-  job.pts.assign(points, points + (size_t)N * k);
-  job.heights.assign(heights, heights + N);
-  job.explicit_heights = true;
-  job.kmin = job.kmax = k;
-  uint64_t total = binom_u64(N, k + 1);
-  uint64_t hi = std::min(rank_hi, total), lo = std::min(rank_lo, hi);
-  std::vector<TileC> tc;
-  tiles_range(N, k, 0, lo, hi, choose_max_cost(hi - lo, default_waves(k, k, 4)), tc);
-  tiles_sorted(tc, job.tiles);
-  int rc = job_upload(job);
+  points_job(job, points, heights, N, k, rank_lo, rank_hi);
+  rc = job_upload(job);
   if (rc) return rc;
   rc = job_launch(job, D->stream);
   if (rc) return rc;
@@ -426,6 +506,84 @@ int bdeg_nvol_points(const int32_t *points, const int64_t *heights, int32_t N, i
   *tie = (int32_t)acc[0].tie;
   if (cells) *cells = acc[0].cells;
   return BDEG_OK;
+}
+
+int bdeg_cells_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, uint64_t rank_lo,
+                      uint64_t rank_hi, uint64_t cap, uint64_t *cell_masks, int64_t *normal_num,
+                      uint64_t *normal_den, uint64_t *n_cells, int32_t *tie) {
+  if (!n_cells || !tie || (cap > 0 && (!cell_masks || !normal_num || !normal_den))) return BDEG_E_ARG;
+  int rc = check_points(points, heights, N, k);
+  if (rc) return rc;
+  int st;
+  Device *D = device_get(&st);
+  if (!D) return st;
+  std::lock_guard<std::mutex> lk(D->mu);
+  Job job;
+  points_job(job, points, heights, N, k, rank_lo, rank_hi);
+  rc = job_upload(job);
+  if (rc) return rc;
+  SysAcc acc;
+  rc = list_cells(D, job, N, k, cap, cell_masks, normal_num, normal_den, n_cells, &acc);
+  if (rc) return rc;
+  *tie = (int32_t)acc.tie;
+  return BDEG_OK;
+}
+
+int bdeg_subdivision(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int32_t lift_bits, uint64_t cap,
+                     int32_t *points, int64_t *heights, uint64_t *cell_masks, int64_t *normal_num,
+                     uint64_t *normal_den, uint64_t *n_cells, bdeg_result *out) {
+  if (!A || !out || !n_cells || !points || !heights || (cap > 0 && (!cell_masks || !normal_num || !normal_den)))
+    return BDEG_E_ARG;
+  *n_cells = 0;
+  bdeg_result res;
+  HostSys hs;
+  if (!prepare_one(A, m, n, seed, lift_bits, 0, res, hs)) {
+    *out = res;
+    return res.status;
+  }
+  int st;
+  Device *D = device_get(&st);
+  if (!D) {
+    res.status = st;
+    *out = res;
+    return st;
+  }
+  std::lock_guard<std::mutex> lk(D->mu);
+  Job job;
+  const uint64_t cand = binom_u64(hs.N, hs.k + 1);
+  for (;;) {
+    std::vector<HostSys> one{hs};
+    job_build_seeded(job, one, choose_max_cost(cand, default_waves(hs.k, hs.k, 4)));
+    int rc = job_upload(job);
+    SysAcc acc{};
+    uint64_t count = 0;
+    if (!rc) rc = list_cells(D, job, hs.N, hs.k, cap, cell_masks, normal_num, normal_den, &count, &acc);
+    if (!rc && hipMemcpyAsync(heights, job.d_hts, (size_t)hs.N * sizeof(int64_t), hipMemcpyDeviceToHost,
+                              D->stream) != hipSuccess)
+      rc = BDEG_E_DEVICE;
+    if (!rc && hipStreamSynchronize(D->stream) != hipSuccess) rc = BDEG_E_DEVICE;
+    if (rc) {
+      res.status = rc;
+      break;
+    }
+    res.attempts = (int32_t)hs.attempt + 1;
+    if (acc.tie) {
+      if (hs.attempt + 1 >= BDEG_MAX_ATTEMPTS) {
+        res.status = BDEG_E_TIE;
+        break;
+      }
+      hs.attempt++;
+      continue;
+    }
+    res.nvol = bdeg_u128{acc.lo, acc.hi};
+    res.cells = acc.cells;
+    res.status = BDEG_OK;
+    *n_cells = count;
+    memcpy(points, hs.pts.data(), hs.pts.size() * sizeof(int32_t));
+    break;
+  }
+  *out = res;
+  return res.status;
 }
 
 int bdeg_plan_units(int32_t N, int32_t k, uint64_t rank_lo, uint64_t rank_hi, uint64_t max_cost,

@@ -88,21 +88,51 @@ void tiles_sorted(std::vector<TileC> &in, std::vector<Tile> &out);
 // ------------------------------------------------------------ lifting
 uint64_t lift_key(uint64_t seed, uint32_t sys_index, uint32_t attempt);
 
+// Device cell list: vertex masks of lower facets, appended through `count`
+// (facets beyond `cap` are counted, not stored).
+struct CellSink {
+  uint64_t *masks;
+  uint64_t cap;
+  uint64_t *count;
+};
+
 // ------------------------------------------------------------ kernels (kernels.hip)
+// enumeration kernel variants
+constexpr int MODE_PLAIN = 0; // volume, cell count and tie flag
+constexpr int MODE_STATS = 1; // also count the work (profiling)
+constexpr int MODE_EMIT = 2;  // also list every lower facet (single-k kernels only)
+
+// host-side handle of one enumeration kernel instantiation
+typedef void (*EnumFn)(const SysDesc *, const int32_t *, const int64_t *, const Tile *, uint32_t, SysAcc *,
+                       DevCounters *, CellSink);
+
 struct LaunchShape {
   int blocks = 0;
   int waves_per_block = 4;
-  bool stats = false; // run the variant that counts its work
+  bool single = false; // every unit launched has N > 32 points: one point group per wavefront
+  int mode = MODE_PLAIN;
+  CellSink sink{nullptr, 0, nullptr}; // MODE_EMIT only
 };
+// point groups per wavefront for N points: 64 / (smallest power of two >= N, at least 8)
+inline int groups_for(int N) { return N <= 8 ? 8 : N <= 16 ? 4 : N <= 32 ? 2 : 1; }
+// units of systems with one point group per wavefront run in their own kernel variant
+inline bool single_group(int N) { return groups_for(N) == 1; }
+inline int npad_log2_for(int N) { return N <= 8 ? 3 : N <= 16 ? 4 : N <= 32 ? 5 : 6; }
 // Launch helpers; all asynchronous on `stream` (a hipStream_t).
 int launch_lift(void *stream, const SysDesc *d_sys, const int32_t *d_active, int n_active,
                 int64_t *d_heights);
-int launch_clear(void *stream, SysAcc *d_acc, int n_sys, DevCounters *d_cnt);
+int launch_clear(void *stream, SysAcc *d_acc, int n_sys, DevCounters *d_cnt, int n_cnt);
 int launch_clear_list(void *stream, SysAcc *d_acc, const int32_t *d_list, int n);
 int launch_enumerate(void *stream, const SysDesc *d_sys, const int32_t *d_pts,
                      const int64_t *d_heights, const Tile *d_tiles, uint32_t n_tiles, SysAcc *d_acc,
                      DevCounters *d_cnt, int kmin, int kmax, LaunchShape shape);
 int device_cu_count();
-int max_enum_blocks(int kmin, int kmax, int waves_per_block); // occupancy-derived persistent grid
+// Inner normals of listed lower facets (one thread per facet): for the facet
+// with vertex mask masks[i] of the N x k points (int32) and heights, num[i*k ..]
+// and den[i] > 0 with alpha = num / den; sets *d_err on a malformed mask or
+// a value outside int64.
+int launch_cell_normals(void *stream, const uint64_t *d_masks, uint64_t n, const int32_t *d_pts,
+                        const int64_t *d_hts, int N, int k, int64_t *d_num, uint64_t *d_den, uint32_t *d_err);
+int max_enum_blocks(int kmin, int kmax, int waves_per_block, bool single); // occupancy-derived persistent grid
 
 } // namespace bdeg

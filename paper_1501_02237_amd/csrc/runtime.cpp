@@ -45,7 +45,7 @@ Device *device_get(int *status) {
 }
 
 int default_waves(int kmin, int kmax, int waves_per_block) {
-  int blocks = max_enum_blocks(kmin, kmax, waves_per_block);
+  int blocks = max_enum_blocks(kmin, kmax, waves_per_block, false);
   return blocks > 0 ? blocks * waves_per_block : 1024;
 }
 
@@ -56,12 +56,6 @@ uint64_t choose_max_cost(uint64_t total, int waves) {
   return per < 256 ? 256 : per;
 }
 
-static int npad_log2_for(int N) {
-  if (N <= 8) return 3;
-  if (N <= 16) return 4;
-  if (N <= 32) return 5;
-  return 6;
-}
 
 void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t max_cost) {
   job.sys.clear();
@@ -90,8 +84,25 @@ void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t ma
     tiles_full(h.N, h.k, (uint32_t)s, max_cost, tc);
   }
   if (job.kmin > job.kmax) job.kmin = job.kmax;
-  tiles_sorted(tc, job.tiles);
+  job_order_units(job, tc);
   job.heights.assign(ht, 0);
+}
+
+void job_order_units(Job &job, std::vector<TileC> &tc) {
+  std::stable_sort(tc.begin(), tc.end(), [&](const TileC &a, const TileC &b) {
+    const bool ga = single_group(job.sys[a.t.sys].N), gb = single_group(job.sys[b.t.sys].N);
+    if (ga != gb) return ga < gb;
+    return a.cost > b.cost;
+  });
+  job.tiles.resize(tc.size());
+  job.granges.clear();
+  for (size_t i = 0; i < tc.size(); i++) {
+    job.tiles[i] = tc[i].t;
+    const bool g = single_group(job.sys[tc[i].t.sys].N);
+    if (job.granges.empty() || job.granges.back().single != g)
+      job.granges.push_back(Job::VariantRange{g, (uint32_t)i, 0});
+    job.granges.back().count++;
+  }
 }
 
 template <typename T>
@@ -119,7 +130,8 @@ int job_upload(Job &job) {
     return rc;
   static_assert(sizeof(SysAcc) == 32, "SysAcc layout");
   if ((rc = grow(&job.d_acc, &job.cap_acc, job.sys.size()))) return rc;
-  if (!job.d_cnt && hipMalloc((void **)&job.d_cnt, sizeof(DevCounters)) != hipSuccess) return BDEG_E_NOMEM;
+  if (!job.d_cnt && hipMalloc((void **)&job.d_cnt, GROUP_SLOTS * sizeof(DevCounters)) != hipSuccess)
+    return BDEG_E_NOMEM;
   if (hipMemcpy(job.d_sys, job.sys.data(), job.sys.size() * sizeof(SysDesc), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(job.d_pts, job.pts.data(), job.pts.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(job.d_tiles, job.tiles.data(), job.tiles.size() * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess)
@@ -132,15 +144,21 @@ int job_upload(Job &job) {
 }
 
 int job_launch_pre(Job &job, hipStream_t stream) {
-  int rc = launch_clear(stream, job.d_acc, (int)job.sys.size(), job.d_cnt);
+  int rc = launch_clear(stream, job.d_acc, (int)job.sys.size(), job.d_cnt, GROUP_SLOTS);
   if (rc) return rc;
   if (!job.explicit_heights) rc = launch_lift(stream, job.d_sys, nullptr, (int)job.sys.size(), job.d_hts);
   return rc;
 }
 
 int job_launch_enum(Job &job, hipStream_t stream) {
-  return launch_enumerate(stream, job.d_sys, job.d_pts, job.d_hts, job.d_tiles, (uint32_t)job.tiles.size(),
-                          job.d_acc, job.d_cnt, job.kmin, job.kmax, job.shape);
+  for (const Job::VariantRange &r : job.granges) {
+    LaunchShape shape = job.shape;
+    shape.single = r.single;
+    int rc = launch_enumerate(stream, job.d_sys, job.d_pts, job.d_hts, job.d_tiles + r.start, r.count, job.d_acc,
+                              job.d_cnt + group_slot(r.single), job.kmin, job.kmax, shape);
+    if (rc) return rc;
+  }
+  return BDEG_OK;
 }
 
 int job_launch(Job &job, hipStream_t stream, hipEvent_t e0, hipEvent_t e1) {
@@ -154,15 +172,25 @@ int job_launch(Job &job, hipStream_t stream, hipEvent_t e0, hipEvent_t e1) {
 
 int job_collect(Job &job, hipStream_t stream, std::vector<SysAcc> &acc, DevCounters *cnt) {
   acc.resize(job.sys.size());
-  DevCounters local;
-  DevCounters *c = cnt ? cnt : &local;
+  DevCounters blocks[GROUP_SLOTS];
   if (!acc.empty() &&
       hipMemcpyAsync(acc.data(), job.d_acc, acc.size() * sizeof(SysAcc), hipMemcpyDeviceToHost, stream) != hipSuccess)
     return BDEG_E_DEVICE;
-  if (hipMemcpyAsync(c, job.d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, stream) != hipSuccess)
+  if (hipMemcpyAsync(blocks, job.d_cnt, sizeof(blocks), hipMemcpyDeviceToHost, stream) != hipSuccess)
     return BDEG_E_DEVICE;
   if (hipStreamSynchronize(stream) != hipSuccess) return BDEG_E_DEVICE;
-  if (c->error) return BDEG_E_DEVICE; // a work unit hit the watchdog
+  DevCounters sum{};
+  for (const DevCounters &b : blocks) {
+    sum.ridges += b.ridges;
+    sum.inner += b.inner;
+    sum.sp_upd += b.sp_upd;
+    sum.pruned += b.pruned;
+    sum.leaves += b.leaves;
+    sum.tiles += b.tiles;
+    sum.error |= b.error;
+  }
+  if (cnt) *cnt = sum;
+  if (sum.error) return BDEG_E_DEVICE; // a work unit hit the watchdog
   return BDEG_OK;
 }
 

@@ -46,6 +46,13 @@ struct Job {
   DevCounters *d_cnt = nullptr;
   size_t cap_sys = 0, cap_pts = 0, cap_hts = 0, cap_tiles = 0, cap_acc = 0;
 
+  // units are ordered by kernel variant; one launch per variant present
+  struct VariantRange {
+    bool single;
+    uint32_t start, count;
+  };
+  std::vector<VariantRange> granges;
+
   LaunchShape shape;
   ~Job();
   void release();
@@ -53,6 +60,11 @@ struct Job {
 
 // Build device descriptors and tiles for `systems` (seeded lifting) into job.
 void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t max_cost);
+// Order units by (kernel variant, decreasing cost) and record the variant ranges.
+void job_order_units(Job &job, std::vector<TileC> &tc);
+// index of a kernel variant among the per-launch counter blocks
+inline int group_slot(bool single) { return single ? 1 : 0; }
+constexpr int GROUP_SLOTS = 2;
 // Upload (growing buffers as needed).
 int job_upload(Job &job);
 // Enqueue clear + lift (pre) and the enumeration; job_launch does both.

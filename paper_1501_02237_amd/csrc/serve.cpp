@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "api_internal.hpp"
+#include "runtime.hpp"
 
 using namespace bdeg;
 
@@ -118,7 +119,7 @@ int bdeg_server::setup_device() {
       hipMalloc((void **)&d_hts, (size_t)max_slots * SLOT_HTS * 8) != hipSuccess ||
       hipMalloc((void **)&d_acc, max_slots * sizeof(SysAcc)) != hipSuccess ||
       hipMalloc((void **)&d_tiles, STEP_TILES_MAX * sizeof(Tile)) != hipSuccess ||
-      hipMalloc((void **)&d_cnt, (BDEG_MAX_K + 1) * sizeof(DevCounters)) != hipSuccess ||
+      hipMalloc((void **)&d_cnt, (BDEG_MAX_K + 1) * GROUP_SLOTS * sizeof(DevCounters)) != hipSuccess ||
       hipMalloc((void **)&d_list, max_slots * sizeof(int32_t)) != hipSuccess)
     return BDEG_E_NOMEM;
   if (hipHostMalloc((void **)&h_tiles, STEP_TILES_MAX * sizeof(Tile), hipHostMallocDefault) != hipSuccess ||
@@ -177,7 +178,7 @@ void bdeg_server::start_attempt(Request *r) {
   d.pt_off = r->slot * SLOT_PTS;
   d.ht_off = r->slot * SLOT_HTS;
   d.lift_bits = r->hs.lift_bits;
-  d.npad_log2 = d.N <= 8 ? 3 : d.N <= 16 ? 4 : d.N <= 32 ? 5 : 6;
+  d.npad_log2 = npad_log2_for(d.N);
   d.lift_key = lift_key(r->hs.seed, 0u, r->hs.attempt); // the single-system stream
   (void)hipMemcpyAsync(d_sys + r->slot, &d, sizeof(SysDesc), hipMemcpyHostToDevice, stream);
   std::vector<TileC> tc;
@@ -263,7 +264,9 @@ void bdeg_server::run() {
     }
     // 3. one step: round-robin quanta over the active requests, then the
     //    units grouped by k (one single-k launch per group, concurrently)
-    std::vector<Tile> byk[BDEG_MAX_K + 1];
+    // units grouped by (k, kernel variant): index k * GROUP_SLOTS + slot
+    constexpr int NB = (BDEG_MAX_K + 1) * GROUP_SLOTS;
+    std::vector<Tile> byk[NB];
     uint32_t nt = 0;
     uint64_t budget_c = STEP_CANDIDATES;
     bool progress = true;
@@ -272,7 +275,7 @@ void bdeg_server::run() {
       for (Request *r : active) {
         if (r->next >= r->tiles.size() || nt >= STEP_TILES_MAX) continue;
         const Tile &t = r->tiles[r->next++];
-        byk[r->hs.k].push_back(t);
+        byk[r->hs.k * GROUP_SLOTS + group_slot(single_group(r->hs.N))].push_back(t);
         nt++;
         uint64_t s0, e0;
         tile_interval(t, r->hs.k, &s0, &e0);
@@ -283,40 +286,46 @@ void bdeg_server::run() {
     }
     int rc = BDEG_OK;
     if (nt > 0) {
-      uint32_t off = 0, start[BDEG_MAX_K + 1];
-      for (int k = 1; k <= BDEG_MAX_K; k++) {
-        start[k] = off;
-        if (!byk[k].empty()) memcpy(h_tiles + off, byk[k].data(), byk[k].size() * sizeof(Tile));
-        off += (uint32_t)byk[k].size();
+      uint32_t off = 0, start[NB];
+      for (int b = 0; b < NB; b++) {
+        start[b] = off;
+        if (!byk[b].empty()) memcpy(h_tiles + off, byk[b].data(), byk[b].size() * sizeof(Tile));
+        off += (uint32_t)byk[b].size();
       }
       if (hipMemcpyAsync(d_tiles, h_tiles, nt * sizeof(Tile), hipMemcpyHostToDevice, stream) != hipSuccess)
         rc = BDEG_E_DEVICE;
-      for (int k = 1; k <= BDEG_MAX_K && !rc; k++)
-        if (!byk[k].empty()) rc = launch_clear(stream, nullptr, 0, d_cnt + k);
+      if (!rc) rc = launch_clear(stream, nullptr, 0, d_cnt, NB);
       if (!rc && hipEventRecord(step_ready, stream) != hipSuccess) rc = BDEG_E_DEVICE;
       for (int k = 1; k <= BDEG_MAX_K && !rc; k++) {
-        if (byk[k].empty()) continue;
+        bool any = false;
+        for (int gs = 0; gs < GROUP_SLOTS; gs++) any |= !byk[k * GROUP_SLOTS + gs].empty();
+        if (!any) continue;
         if (hipStreamWaitEvent(kstream[k], step_ready, 0) != hipSuccess) {
           rc = BDEG_E_DEVICE;
           break;
         }
-        LaunchShape shape;
-        rc = launch_enumerate(kstream[k], d_sys, d_pts, d_hts, d_tiles + start[k], (uint32_t)byk[k].size(), d_acc,
-                              d_cnt + k, k, k, shape);
+        for (int gs = 0; gs < GROUP_SLOTS && !rc; gs++) {
+          const int b = k * GROUP_SLOTS + gs;
+          if (byk[b].empty()) continue;
+          LaunchShape shape;
+          shape.single = gs == group_slot(true);
+          rc = launch_enumerate(kstream[k], d_sys, d_pts, d_hts, d_tiles + start[b], (uint32_t)byk[b].size(), d_acc,
+                                d_cnt + b, k, k, shape);
+        }
         if (!rc && (hipEventRecord(kdone[k], kstream[k]) != hipSuccess ||
                     hipStreamWaitEvent(stream, kdone[k], 0) != hipSuccess))
           rc = BDEG_E_DEVICE;
       }
     }
     // 4. partial sums of all active slots
-    DevCounters cnt[BDEG_MAX_K + 1];
+    static DevCounters cnt[(BDEG_MAX_K + 1) * GROUP_SLOTS];
     if (!rc && hipMemcpyAsync(h_acc, d_acc, max_slots * sizeof(SysAcc), hipMemcpyDeviceToHost, stream) != hipSuccess)
       rc = BDEG_E_DEVICE;
     if (!rc && hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, stream) != hipSuccess)
       rc = BDEG_E_DEVICE;
     if (!rc && hipStreamSynchronize(stream) != hipSuccess) rc = BDEG_E_DEVICE;
-    for (int k = 1; k <= BDEG_MAX_K && !rc; k++)
-      if (!byk[k].empty() && cnt[k].error) rc = BDEG_E_DEVICE;
+    for (int b = 0; b < (BDEG_MAX_K + 1) * GROUP_SLOTS && !rc; b++)
+      if (!byk[b].empty() && cnt[b].error) rc = BDEG_E_DEVICE;
     // 5. retire finished requests, relift tied ones
     std::vector<Request *> still;
     for (Request *r : active) {

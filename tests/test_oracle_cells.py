@@ -1,7 +1,7 @@
 """Pins of the oracle's cell list (lower facets with inner normals).
 
 The cells of the regular subdivision are the lower facets of the lifted point
-set; each has a unique inner normal (alpha, 1) (Section 4, eq.
+set; each has a unique inner normal (alpha, 1) (Section 5, eq.
 ``lower-d-face-again``), listed as alpha = num / den with den the cell's
 normalized volume.  Pinned against hand-worked lower hulls of the paper's
 unit-square example, against qhull's convex hull of the lifted points, and
