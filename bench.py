@@ -112,6 +112,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=4000)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a dispatch of known "
+                         "traffic, for scaling hardware byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {a.gpus}); "
@@ -125,6 +128,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if a.calibrate_copy_mib > 0:
+        src = torch.ones(a.calibrate_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {a.calibrate_copy_mib} MiB read + {a.calibrate_copy_mib} MiB written")
+        del src, dst
 
     s2 = gen.cfg2_system()
     N2, k2 = s2.n + 1, s2.n - s2.m

@@ -88,6 +88,9 @@ typedef struct {
   uint64_t pruned;            /* prefixes cut because the new point is affinely dependent */
   uint64_t leaves;            /* candidates tested with a nonzero determinant */
   uint64_t tiles;             /* work units processed */
+  uint64_t ridge_steps;       /* wavefront iterations of the ridge loops (one ridge per lane group) */
+  uint64_t leaf_steps;        /* wavefront iterations of the leaf loops (one candidate per lane group) */
+  uint64_t empty_steps;       /* leaf iterations in which no lane group had a candidate with D != 0 */
   float kernel_ms;            /* device time of the enumeration kernel, HIP events */
   float total_ms;             /* device time of the whole device pass (clear, lift, enumerate) */
 } bdeg_stats;

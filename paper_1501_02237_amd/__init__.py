@@ -62,6 +62,7 @@ class Stats(ctypes.Structure):
     _fields_ = [
         ("ridges", ctypes.c_uint64), ("inner_nodes", ctypes.c_uint64), ("spatial_updates", ctypes.c_uint64),
         ("pruned", ctypes.c_uint64), ("leaves", ctypes.c_uint64), ("tiles", ctypes.c_uint64),
+        ("ridge_steps", ctypes.c_uint64), ("leaf_steps", ctypes.c_uint64), ("empty_steps", ctypes.c_uint64),
         ("kernel_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
     ]
 

@@ -459,6 +459,9 @@ int bdeg_batch_profile(bdeg_batch *b) {
   b->stats.spatial_updates = cnt.sp_upd;
   b->stats.pruned = cnt.pruned;
   b->stats.leaves = cnt.leaves;
+  b->stats.ridge_steps = cnt.rsteps;
+  b->stats.leaf_steps = cnt.lsteps;
+  b->stats.empty_steps = cnt.lempty;
   b->stats.tiles = cnt.tiles;
   return BDEG_OK;
 }

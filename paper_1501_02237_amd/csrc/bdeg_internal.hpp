@@ -53,6 +53,7 @@ struct SysAcc {
 // Device-wide counters (zeroed per run).
 struct DevCounters {
   uint64_t ridges, inner, sp_upd, pruned, leaves, tiles;
+  uint64_t rsteps, lsteps, lempty; // wavefront loop iterations (ridge, leaf, leaf without candidates)
   uint32_t next_tile; // dynamic work queue head
   uint32_t error;     // a work unit exceeded its step budget (watchdog)
 };

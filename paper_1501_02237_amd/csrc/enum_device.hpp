@@ -111,7 +111,7 @@ struct Ctx {
   // error, so no wavefront can loop without end
   uint32_t left;
   // work counters of the profiling variant
-  uint32_t leaves, ridges, inner, sp_upd, pruned;
+  uint32_t leaves, ridges, inner, sp_upd, pruned, rsteps, lsteps, lempty;
   // cell list of the emitting variant
   CellSink sink;
 };
@@ -212,7 +212,11 @@ template <class CX>
 __device__ __forceinline__ void decide(CX &cx, uint64_t m_neg, uint64_t m_nz, uint64_t m_sc, uint64_t excl,
                                        int32_t sig, int cand, uint64_t fixed, int ridge) {
   const uint64_t has = m_sc & cx.top_bits;
-  if constexpr (CX::stats) cx.leaves += (uint32_t)__builtin_popcountll(has);
+  if constexpr (CX::stats) {
+    cx.leaves += (uint32_t)__builtin_popcountll(has);
+    cx.lsteps++;
+    cx.lempty += has == 0;
+  }
   const uint64_t ok = has & ~any_group(cx, m_neg & ~excl);
   if (ok == 0) return;
   const uint64_t zero = ok & any_group(cx, ~(m_nz | excl));
@@ -257,7 +261,26 @@ __device__ __forceinline__ void leaves_uniform(CX &cx, const St<1> &st, int hi_c
   const bool prevneg = st.prev < 0;
   const uint64_t excl = ~cx.valid_lanes | cx.chosen_rep;
   const uint64_t fixed = CX::emit ? (cx.chosen_rep & group0_mask(cx)) : 0ull;
-  if (hi_c < lo_c || !charge(cx, (hi_c - lo_c + G) / G)) return;
+  if (hi_c < lo_c) return;
+  if constexpr (CX::single) {
+    // one group: visit only the candidates with D = sigma_c != 0 (the chosen
+    // points have a zero residual and drop out by themselves)
+    const uint64_t range = ((2ull << hi_c) - 1) & ~((1ull << lo_c) - 1);
+    uint64_t todo = ballot(sig != 0) & cx.valid_lanes & range;
+    if (!charge(cx, __builtin_popcountll(todo))) return;
+    while (todo) {
+      const int c0 = 63 - __builtin_clzll(todo);
+      todo &= ~(1ull << c0);
+      const int32_t sc = rl32(sig, c0), h1c = rl32(H1, c0), h0c = rl32(H0, c0);
+      const Cross t = cross_sign(sc, h1c, h0c, sig, H1, H0);
+      const bool flip = (sc < 0) != prevneg;
+      const uint64_t m_neg = ballot(t.nz && (t.lt != flip));
+      const uint64_t m_nz = ballot(t.nz);
+      decide(cx, m_neg, m_nz, ~0ull, excl | (1ull << c0), sig, c0, fixed, -1);
+    }
+    return;
+  }
+  if (!charge(cx, (hi_c - lo_c + G) / G)) return;
   for (int c0 = hi_c; c0 >= lo_c; c0 -= G) {
     const int cg = c0 - cx.g;
     const bool ok = cg >= lo_c;
@@ -369,7 +392,10 @@ struct Level {
           r.H1 = (int32_t)(h >> 31);
           r.H0 = (int32_t)((uint32_t)h & LOW31);
           r.prev = piv;
-          if constexpr (S) cx.ridges++;
+          if constexpr (S) {
+            cx.ridges++;
+            cx.rsteps++;
+          }
           cx.chosen_rep |= cx.rep_unit << c;
           int lhi = c - 1, llo = 0;
           if (T + 2 < cx.L) { // the candidate itself is fixed (rank-range units)
@@ -408,13 +434,25 @@ struct Level {
             const uint32_t n_alive = (uint32_t)__builtin_popcountll(m_alive & cx.rep_unit);
             cx.ridges += n_alive;
             cx.pruned += (uint32_t)ngr - n_alive;
+            cx.rsteps++;
           }
           if (!m_alive) continue;
           const uint64_t excl = ~cx.valid_lanes | cx.chosen_rep | diag_lanes(cx, c);
           const uint64_t fixed = CX::emit ? (cx.chosen_rep & group0_mask(cx)) : 0ull;
-          // candidates: group q tests cc - q for cc = c-1 .. 0
-          if (!charge(cx, c)) continue;
-          for (int cc = c - 1; cc >= 0; --cc) {
+          // candidates: group q tests cc - q for cc = c-1 .. 0, visiting only
+          // the cc for which some live group's point cc - q has D != 0 (lane
+          // j of group q stands for cc = j + q; chosen and ridge points have
+          // a zero residual and drop out by themselves)
+          const uint64_t nzl = ballot(alive && sig != 0) & cx.valid_lanes;
+          const int npl = cx.npl();
+          const uint64_t gm0 = (1ull << cx.npad()) - 1;
+          uint64_t todo = 0;
+          for (int q = 0; q < G; q++) todo |= ((nzl >> (q << npl)) & gm0) << q;
+          todo &= (1ull << c) - 1;
+          if (!charge(cx, __builtin_popcountll(todo))) continue;
+          while (todo) {
+            const int cc = 63 - __builtin_clzll(todo);
+            todo &= ~(1ull << cc);
             const int cq = cc - cx.g;
             const bool lok = cq >= 0;
             const int src2 = cx.g * cx.npad() + (lok ? cq : 0);
@@ -510,7 +548,7 @@ __device__ __forceinline__ void run_unit(const Tile &tl, const SysDesc &sd, cons
   cx.acc = 0;
   cx.cells = 0;
   cx.tie = 0;
-  cx.leaves = cx.ridges = cx.inner = cx.sp_upd = cx.pruned = 0;
+  cx.leaves = cx.ridges = cx.inner = cx.sp_upd = cx.pruned = cx.rsteps = cx.lsteps = cx.lempty = 0;
   cx.sink = sink;
   {
     // every loop step of a unit is charged to a candidate below it, and a
@@ -546,6 +584,9 @@ __device__ __forceinline__ void run_unit(const Tile &tl, const SysDesc &sd, cons
       atomicAdd((unsigned long long *)&cnt->inner, (unsigned long long)cx.inner);
       atomicAdd((unsigned long long *)&cnt->sp_upd, (unsigned long long)cx.sp_upd);
       atomicAdd((unsigned long long *)&cnt->leaves, (unsigned long long)cx.leaves);
+      atomicAdd((unsigned long long *)&cnt->rsteps, (unsigned long long)cx.rsteps);
+      atomicAdd((unsigned long long *)&cnt->lsteps, (unsigned long long)cx.lsteps);
+      atomicAdd((unsigned long long *)&cnt->lempty, (unsigned long long)cx.lempty);
       atomicAdd((unsigned long long *)&cnt->pruned, (unsigned long long)cx.pruned);
       atomicAdd((unsigned long long *)&cnt->tiles, 1ull);
     }

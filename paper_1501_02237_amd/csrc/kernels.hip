@@ -40,6 +40,7 @@ __global__ void clear_kernel(SysAcc *__restrict__ acc, int n_sys, DevCounters *_
   if (i < n_cnt && cnt_all) {
     DevCounters *cnt = cnt_all + i;
     cnt->ridges = cnt->inner = cnt->sp_upd = cnt->pruned = cnt->leaves = cnt->tiles = 0;
+    cnt->rsteps = cnt->lsteps = cnt->lempty = 0;
     cnt->next_tile = 0;
     cnt->error = 0;
   }

@@ -186,6 +186,9 @@ int job_collect(Job &job, hipStream_t stream, std::vector<SysAcc> &acc, DevCount
     sum.sp_upd += b.sp_upd;
     sum.pruned += b.pruned;
     sum.leaves += b.leaves;
+    sum.rsteps += b.rsteps;
+    sum.lsteps += b.lsteps;
+    sum.lempty += b.lempty;
     sum.tiles += b.tiles;
     sum.error |= b.error;
   }

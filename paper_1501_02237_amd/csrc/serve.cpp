@@ -48,6 +48,7 @@ constexpr int MAX_SLOTS = 4096;
 constexpr uint32_t STEP_TILES_MAX = 32768;
 constexpr uint64_t STEP_CANDIDATES = 24000000; // quantum of one step
 constexpr uint64_t UNIT_COST = 2048;           // work-unit size cap for served requests
+constexpr size_t PROLOGUE_THREADS = 8;         // host prologue workers for a burst of submissions
 
 using Clock = std::chrono::steady_clock;
 
@@ -181,9 +182,12 @@ void bdeg_server::start_attempt(Request *r) {
   d.npad_log2 = npad_log2_for(d.N);
   d.lift_key = lift_key(r->hs.seed, 0u, r->hs.attempt); // the single-system stream
   (void)hipMemcpyAsync(d_sys + r->slot, &d, sizeof(SysDesc), hipMemcpyHostToDevice, stream);
+  // units are taken round-robin across requests in small steps, so their
+  // order within a request does not matter: no sort
   std::vector<TileC> tc;
   tiles_full(d.N, d.k, (uint32_t)r->slot, UNIT_COST, tc);
-  tiles_sorted(tc, r->tiles);
+  r->tiles.resize(tc.size());
+  for (size_t i = 0; i < tc.size(); i++) r->tiles[i] = tc[i].t;
   r->next = 0;
 }
 
@@ -223,9 +227,23 @@ void bdeg_server::run() {
       fresh.assign(submitted.begin(), submitted.end());
       submitted.clear();
     }
-    // 1. host prologue
+    // 1. host prologue (a burst is split over worker threads; results are
+    //    then queued in arrival order)
+    {
+      auto work = [&](size_t lo, size_t hi) {
+        for (size_t i = lo; i < hi; i++) {
+          Request *r = fresh[i];
+          r->need_dev = prepare_one(r->A.data(), r->m, r->n, r->seed, r->bits, 0, r->res, r->hs);
+        }
+      };
+      const size_t nf = fresh.size();
+      const size_t nt = nf >= 32 ? std::min<size_t>(PROLOGUE_THREADS, nf / 16) : 1;
+      std::vector<std::thread> th;
+      for (size_t t = 1; t < nt; t++) th.emplace_back(work, nf * t / nt, nf * (t + 1) / nt);
+      work(0, nf / nt);
+      for (auto &x : th) x.join();
+    }
     for (Request *r : fresh) {
-      r->need_dev = prepare_one(r->A.data(), r->m, r->n, r->seed, r->bits, 0, r->res, r->hs);
       if (!r->need_dev) {
         finish(r, r->res.status);
         continue;

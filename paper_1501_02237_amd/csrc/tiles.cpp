@@ -15,8 +15,33 @@
 
 namespace bdeg {
 
+// C(n, r) for 0 <= n, r <= 64, saturated at UINT64_MAX (computed once).
+namespace {
+struct BinomTable {
+  uint64_t c[65][65];
+  BinomTable() {
+    for (int n = 0; n <= 64; n++)
+      for (int r = 0; r <= 64; r++) {
+        if (r > n) {
+          c[n][r] = 0;
+        } else if (r == 0 || r == n) {
+          c[n][r] = 1;
+        } else {
+          const uint64_t a = c[n - 1][r - 1], b = c[n - 1][r];
+          c[n][r] = (a > UINT64_MAX - b) ? UINT64_MAX : a + b;
+        }
+      }
+  }
+};
+const BinomTable &binom_table() {
+  static const BinomTable t;
+  return t;
+}
+} // namespace
+
 uint64_t binom_u64(int n, int r) {
   if (r < 0 || n < 0 || r > n) return 0;
+  if (n <= 64) return binom_table().c[n][r];
   if (r > n - r) r = n - r;
   u128 c = 1;
   for (int i = 1; i <= r; i++) {
