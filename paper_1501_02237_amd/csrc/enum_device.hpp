@@ -200,7 +200,43 @@ __device__ __forceinline__ int32_t fetch_diag(const CX &cx, int32_t v, int c, in
     return bp32(v, src);
 }
 
+// Leaf test in sign-normalised form.  Each lane keeps a candidate view of its
+// point j at the current ridge: a_j = sign(prev) |sigma_j| and
+// b_j = sign(prev) sign(sigma_j) h_j (both height halves).  For candidate c
+// (D = sigma_c) and point j,
+//     t' = a_c h_j - b_c sigma_j = sign(D prev) (sigma_c h_j - h_c sigma_j),
+// whose sign is that of D s_j: point j lies below the candidate's hyperplane
+// exactly when t' < 0.  With h = H1 2^31 + H0, t' = 2^31 C + lo, 0 <= lo < 2^31,
+// so t' < 0 exactly when C < 0, and t' = 0 exactly when C = lo = 0.
+struct View {
+  int32_t a, b1, b0;
+};
+__device__ __forceinline__ View cand_view(int32_t sig, int32_t H1, int32_t H0, bool prevneg) {
+  const int32_t mag = sig < 0 ? -sig : sig;
+  const bool f = (sig < 0) != prevneg;
+  View v;
+  v.a = prevneg ? -mag : mag;
+  v.b1 = f ? -H1 : H1;
+  v.b0 = f ? -H0 : H0;
+  return v;
+}
+struct Cross {
+  int64_t C;
+  uint32_t lo;
+};
+__device__ __forceinline__ Cross cross_view(int32_t a, int32_t b1, int32_t b0, int32_t sig, int32_t H1,
+                                            int32_t H0) {
+  const int64_t A = (int64_t)a * H1 - (int64_t)b1 * sig;
+  const int64_t B = (int64_t)a * H0 - (int64_t)b0 * sig;
+  Cross r;
+  r.C = A + (B >> 31);
+  r.lo = (uint32_t)B & LOW31;
+  return r;
+}
+
 // Decide one leaf step: group q tests its candidate, point cand - q.
+//   m_neg lanes whose point lies strictly below their group's candidate hyperplane
+//   t     this lane's t' (for the zero test, needed only when a group survives)
 //   m_sc  groups whose candidate exists and has D != 0 (all of their lanes set)
 //   excl  lanes outside the test: padding, chosen points, the candidate
 // A group with a point strictly below the candidate's hyperplane rejects
@@ -209,7 +245,7 @@ __device__ __forceinline__ int32_t fetch_diag(const CX &cx, int32_t v, int c, in
 // lower facet.  For the cell list: `fixed` holds the points every group
 // shares and, when ridge >= 0, group q's ridge adds point ridge - q.
 template <class CX>
-__device__ __forceinline__ void decide(CX &cx, uint64_t m_neg, uint64_t m_nz, uint64_t m_sc, uint64_t excl,
+__device__ __forceinline__ void decide(CX &cx, uint64_t m_neg, const Cross &t, uint64_t m_sc, uint64_t excl,
                                        int32_t sig, int cand, uint64_t fixed, int ridge) {
   const uint64_t has = m_sc & cx.top_bits;
   if constexpr (CX::stats) {
@@ -219,6 +255,7 @@ __device__ __forceinline__ void decide(CX &cx, uint64_t m_neg, uint64_t m_nz, ui
   }
   const uint64_t ok = has & ~any_group(cx, m_neg & ~excl);
   if (ok == 0) return;
+  const uint64_t m_nz = ballot((t.C != 0) | (t.lo != 0));
   const uint64_t zero = ok & any_group(cx, ~(m_nz | excl));
   if (zero) cx.tie = 1;
   const int npl = cx.npl();
@@ -233,23 +270,6 @@ __device__ __forceinline__ void decide(CX &cx, uint64_t m_neg, uint64_t m_nz, ui
       emit_cell(cx, v);
     }
   }
-}
-
-// Sign pieces of t = sc * h_j - hc * sig_j with h = H1 * 2^31 + H0:
-// t = 2^31 * C + Blo with C = A + (B >> 31), Blo = B mod 2^31.
-struct Cross {
-  bool lt, nz;
-};
-__device__ __forceinline__ Cross cross_sign(int32_t sc, int32_t h1c, int32_t h0c, int32_t sig, int32_t H1,
-                                            int32_t H0) {
-  const int64_t A = (int64_t)sc * H1 - (int64_t)h1c * sig;
-  const int64_t B = (int64_t)sc * H0 - (int64_t)h0c * sig;
-  const int64_t C = A + (B >> 31);
-  const uint32_t Blo = (uint32_t)B & LOW31;
-  Cross r;
-  r.lt = C < 0;
-  r.nz = (C != 0) | (Blo != 0);
-  return r;
 }
 
 // Leaves of one ridge whose state is identical in every group: the groups
@@ -271,29 +291,25 @@ __device__ __forceinline__ void leaves_uniform(CX &cx, const St<1> &st, int hi_c
     while (todo) {
       const int c0 = 63 - __builtin_clzll(todo);
       todo &= ~(1ull << c0);
-      const int32_t sc = rl32(sig, c0), h1c = rl32(H1, c0), h0c = rl32(H0, c0);
-      const Cross t = cross_sign(sc, h1c, h0c, sig, H1, H0);
+      // unnormalised t = sigma_c h_j - h_c sigma_j, its sign flipped by the
+      // (wave-uniform) sign of D prev
+      const int32_t sc = rl32(sig, c0);
+      const Cross t = cross_view(sc, rl32(H1, c0), rl32(H0, c0), sig, H1, H0);
       const bool flip = (sc < 0) != prevneg;
-      const uint64_t m_neg = ballot(t.nz && (t.lt != flip));
-      const uint64_t m_nz = ballot(t.nz);
-      decide(cx, m_neg, m_nz, ~0ull, excl | (1ull << c0), sig, c0, fixed, -1);
+      const uint64_t m_neg = ballot(((t.C != 0) | (t.lo != 0)) && ((t.C < 0) != flip));
+      decide(cx, m_neg, t, ~0ull, excl | (1ull << c0), sig, c0, fixed, -1);
     }
     return;
   }
   if (!charge(cx, (hi_c - lo_c + G) / G)) return;
+  const View v = cand_view(sig, H1, H0, prevneg);
   for (int c0 = hi_c; c0 >= lo_c; c0 -= G) {
     const int cg = c0 - cx.g;
     const bool ok = cg >= lo_c;
     const int src = cx.g * cx.npad() + (ok ? cg : 0);
-    const int32_t sc = fetch_diag(cx, sig, c0, src);
-    const int32_t h1c = fetch_diag(cx, H1, c0, src);
-    const int32_t h0c = fetch_diag(cx, H0, c0, src);
-    const Cross t = cross_sign(sc, h1c, h0c, sig, H1, H0);
-    const bool flip = (sc < 0) != prevneg;
-    const uint64_t m_neg = ballot(t.nz && (t.lt != flip));
-    const uint64_t m_nz = ballot(t.nz);
-    const uint64_t m_sc = ballot(ok && sc != 0);
-    decide(cx, m_neg, m_nz, m_sc, excl | diag_lanes(cx, c0), sig, c0, fixed, -1);
+    const int32_t a = fetch_diag(cx, v.a, c0, src);
+    const Cross t = cross_view(a, fetch_diag(cx, v.b1, c0, src), fetch_diag(cx, v.b0, c0, src), sig, H1, H0);
+    decide(cx, ballot(t.C < 0), t, ballot(ok && a != 0), excl | diag_lanes(cx, c0), sig, c0, fixed, -1);
   }
 }
 
@@ -444,6 +460,8 @@ struct Level {
           // j of group q stands for cc = j + q; chosen and ridge points have
           // a zero residual and drop out by themselves)
           const uint64_t nzl = ballot(alive && sig != 0) & cx.valid_lanes;
+          const View v = cand_view(sig, H1, H0, pivneg);
+          const int base = cx.g * cx.npad() - cx.g; // lane of point cc - g is base + cc
           const int npl = cx.npl();
           const uint64_t gm0 = (1ull << cx.npad()) - 1;
           uint64_t todo = 0;
@@ -453,16 +471,13 @@ struct Level {
           while (todo) {
             const int cc = 63 - __builtin_clzll(todo);
             todo &= ~(1ull << cc);
-            const int cq = cc - cx.g;
-            const bool lok = cq >= 0;
-            const int src2 = cx.g * cx.npad() + (lok ? cq : 0);
-            const int32_t sc = bp32(sig, src2), hc1 = bp32(H1, src2), hc0 = bp32(H0, src2);
-            const Cross t = cross_sign(sc, hc1, hc0, sig, H1, H0);
-            const bool flip = (sc < 0) != pivneg;
-            const uint64_t m_neg = ballot(t.nz && (t.lt != flip));
-            const uint64_t m_nz = ballot(t.nz);
-            const uint64_t m_sc = ballot(lok && alive && sc != 0);
-            decide(cx, m_neg, m_nz, m_sc, excl | diag_lanes(cx, cc), sig, cc, fixed, c);
+            // cc < g: no candidate in group g (the fetch reads a lane of the
+            // group below, in range, and is masked out of m_sc)
+            const int src2 = base + cc;
+            const int32_t a = bp32(v.a, src2);
+            const Cross t = cross_view(a, bp32(v.b1, src2), bp32(v.b0, src2), sig, H1, H0);
+            const uint64_t m_sc = ballot(cc >= cx.g && alive && a != 0);
+            decide(cx, ballot(t.C < 0), t, m_sc, excl | diag_lanes(cx, cc), sig, cc, fixed, c);
           }
         }
       }
