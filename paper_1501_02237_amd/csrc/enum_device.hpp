@@ -73,6 +73,13 @@ struct St {
   int32_t prev;             // the pivot that produced this state
 };
 
+// Per-wave results of the current work unit (in LDS, written by lane 0).
+struct Tally {
+  unsigned long long acc; // sum of |D| over lower facets
+  uint32_t cells;         // lower facets
+  uint32_t tie;           // a non-generic lower face was seen
+};
+
 // MODE: MODE_PLAIN, MODE_STATS (also count the work) or MODE_EMIT (also list
 // every lower facet found).  GG = 1: one point group fills the wave (N > 32),
 // a compile-time fact that removes the sibling-ridge path and turns gathers
@@ -104,8 +111,10 @@ struct Ctx {
   uint64_t rep_unit;    // bit 0 of every group
   uint64_t top_bits;    // bit npad-1 of every group (the groups' bit fields)
   uint64_t chosen_rep;  // chosen points, replicated in every group
-  uint64_t acc;         // sum of |D| of lower facets in this unit
-  uint32_t cells, tie;
+  // the unit's sum of |D| over lower facets, cell count and tie flag live in
+  // a per-wave LDS slot: they change only when a cell is found, and kept in
+  // registers they would be copied at every level of the loop nest
+  struct Tally *tally;
   // watchdog: loop steps left for this unit (a budget derived from the unit's
   // candidate count); running out abandons the unit and reports a device
   // error, so no wavefront can loop without end
@@ -257,18 +266,24 @@ __device__ __forceinline__ void decide(CX &cx, uint64_t m_neg, const Cross &t, u
   if (ok == 0) return;
   const uint64_t m_nz = ballot((t.C != 0) | (t.lo != 0));
   const uint64_t zero = ok & any_group(cx, ~(m_nz | excl));
-  if (zero) cx.tie = 1;
   const int npl = cx.npl();
+  uint64_t add = 0;
+  uint32_t found = 0;
   for (uint64_t a = ok & ~zero; a; a &= a - 1) {
     const int q = __builtin_ctzll(a) >> npl;
     const int32_t sv = rl32(sig, (q << npl) + cand - q);
-    cx.acc += (uint64_t)(sv < 0 ? -(int64_t)sv : (int64_t)sv);
-    cx.cells++;
+    add += (uint64_t)(sv < 0 ? -(int64_t)sv : (int64_t)sv);
+    found++;
     if constexpr (CX::emit) {
       uint64_t v = fixed | (1ull << (cand - q));
       if (ridge >= 0) v |= 1ull << (ridge - q);
       emit_cell(cx, v);
     }
+  }
+  if (lane_id() == 0) {
+    cx.tally->acc += add;
+    cx.tally->cells += found;
+    if (zero) cx.tally->tie = 1;
   }
 }
 
@@ -536,7 +551,7 @@ __device__ __forceinline__ void process_tile(CX &cx, const SysDesc &sd, const in
 template <int KLO, int KHI, int MODE, int GG>
 __device__ __forceinline__ void run_unit(const Tile &tl, const SysDesc &sd, const int32_t *__restrict__ pts,
                                          const int64_t *__restrict__ hts, SysAcc *__restrict__ acc,
-                                         DevCounters *__restrict__ cnt, const CellSink &sink) {
+                                         DevCounters *__restrict__ cnt, const CellSink &sink, Tally *tally) {
   using CX = Ctx<MODE, GG>;
   constexpr bool S = CX::stats;
   const int lane = lane_id();
@@ -560,9 +575,12 @@ __device__ __forceinline__ void run_unit(const Tile &tl, const SysDesc &sd, cons
   cx.rep_unit = unit;
   cx.top_bits = top;
   cx.valid_lanes = vl;
-  cx.acc = 0;
-  cx.cells = 0;
-  cx.tie = 0;
+  cx.tally = tally;
+  if (lane == 0) {
+    tally->acc = 0;
+    tally->cells = 0;
+    tally->tie = 0;
+  }
   cx.leaves = cx.ridges = cx.inner = cx.sp_upd = cx.pruned = cx.rsteps = cx.lsteps = cx.lempty = 0;
   cx.sink = sink;
   {
@@ -587,12 +605,14 @@ __device__ __forceinline__ void run_unit(const Tile &tl, const SysDesc &sd, cons
   const bool abandoned = cx.left == 0;
   if (lane == 0 && abandoned) atomicOr(&cnt->error, 1u);
   if (lane == 0 && !abandoned) {
-    if (cx.acc | cx.cells | cx.tie) {
+    const unsigned long long sum = tally->acc;
+    const uint32_t cells = tally->cells, tie = tally->tie;
+    if (sum | cells | tie) {
       SysAcc *a = &acc[tl.sys];
-      const unsigned long long old = atomicAdd((unsigned long long *)&a->lo, (unsigned long long)cx.acc);
-      if (old + cx.acc < old) atomicAdd((unsigned long long *)&a->hi, 1ull);
-      atomicAdd((unsigned long long *)&a->cells, (unsigned long long)cx.cells);
-      if (cx.tie) atomicOr(&a->tie, 1u);
+      const unsigned long long old = atomicAdd((unsigned long long *)&a->lo, sum);
+      if (old + sum < old) atomicAdd((unsigned long long *)&a->hi, 1ull);
+      atomicAdd((unsigned long long *)&a->cells, (unsigned long long)cells);
+      if (tie) atomicOr(&a->tie, 1u);
     }
     if constexpr (S) {
       atomicAdd((unsigned long long *)&cnt->ridges, (unsigned long long)cx.ridges);
@@ -609,15 +629,21 @@ __device__ __forceinline__ void run_unit(const Tile &tl, const SysDesc &sd, cons
 }
 
 // Waves per SIMD each depth is compiled for: the register budget grows with k
-// (one residual row per level), so deeper kernels trade occupancy for no spills.
-constexpr int waves_for_depth(int k) { return k <= 3 ? 8 : k <= 7 ? 7 : k == 8 ? 6 : k == 9 ? 5 : k <= 11 ? 4 : 3; }
+// (one residual row per level), so deeper kernels trade occupancy for no
+// spills.  The single-group variant needs fewer registers (no sibling-ridge
+// path): at k = 10 it fits five waves.
+constexpr int waves_for_depth(int k, int gg) {
+  return k <= 3 ? 8 : k <= 7 ? 7 : k == 8 ? 6 : k == 9 ? 5 : k == 10 ? (gg == 1 ? 5 : 4) : k == 11 ? 4 : 3;
+}
 
 template <int KLO, int KHI, int MODE, int GG>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for_depth(KHI))))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for_depth(KHI, GG))))
 enum_kernel(const SysDesc *__restrict__ sys, const int32_t *__restrict__ pts, const int64_t *__restrict__ hts,
             const Tile *__restrict__ tiles, uint32_t n_tiles, SysAcc *__restrict__ acc,
             DevCounters *__restrict__ cnt, CellSink sink) {
   const int lane = lane_id();
+  __shared__ Tally tallies[4]; // one per wavefront of the block (at most 256 threads)
+  Tally *tally = &tallies[threadIdx.x >> 6];
   for (;;) {
     uint32_t t = 0;
     if (lane == 0) t = atomicAdd(&cnt->next_tile, 1u);
@@ -625,7 +651,7 @@ enum_kernel(const SysDesc *__restrict__ sys, const int32_t *__restrict__ pts, co
     if (t >= n_tiles) break;
     const Tile tl = tiles[t];
     const SysDesc sd = sys[tl.sys];
-    run_unit<KLO, KHI, MODE, GG>(tl, sd, pts, hts, acc, cnt, sink);
+    run_unit<KLO, KHI, MODE, GG>(tl, sd, pts, hts, acc, cnt, sink, tally);
   }
 }
 
