@@ -17,6 +17,7 @@ Prints ONE JSON line.  Only one GPU is used: --gpus above 1 exits.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -27,6 +28,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_ALU = 256 * 4 * 16 * 2.4e9  # 32-bit integer VALU lane-ops/s: CUs x SIMDs x lanes x clock
+
+# HBM traffic of one headline enumeration launch, from the rocprofv3 FETCH_SIZE
+# and WRITE_SIZE passes summarised in profiles/enum_kernel_quiver28_pmc.md (KiB
+# per dispatch, mean of the timed dispatches), each scaled by what the counter
+# reads for a device copy of known size in the same run (FETCH_SIZE reads half
+# of the 256 MiB copied, WRITE_SIZE all of it).  Valid only for the kernel
+# source the counters were taken on; any change to it makes `traffic` null.
+TRAFFIC = {
+    "sources": ("enum_device.hpp", "exact_div.hpp", "kernels_k8.hip"),
+    "sha256": "4a029360e9152ccdcb38d7394f0540e2a5ef5124720511e3d55d135e575e6107",
+    "fetch_kib": 4388.98, "fetch_scale": 262144.0 / 131089.0,
+    "write_kib": 1966.16, "write_scale": 262144.0 / 262144.0,
+}
+
+
+def traffic_bytes():
+    h = hashlib.sha256()
+    for f in TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, "paper_1501_02237_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["sha256"]:
+        return None
+    return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
 
 
 def ops_per_launch(stats: dict, N: int, k: int) -> float:
@@ -266,7 +290,7 @@ def main():
         "config": {"workload": "plain quiver-like system n=28 m=20 k=8 N=29, heights < 2^20, device-resident",
                    "candidates": cand2, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU, "unit": "int32 lane-ops/s",
-                     "frac": achieved / PEAK_ALU, "traffic": None},
+                     "frac": achieved / PEAK_ALU, "traffic": traffic_bytes()},
         "cpu_baseline": cpu,
         "extra": extra,
     }
