@@ -18,6 +18,10 @@ What it computes, plainly and exactly (paper Sections 2 and 4):
     - k = 0: nvol = 1 (a finite set of points, each of degree 1).
 * ``oracle_nvol_points(points, heights)`` -> the same volume sum for a caller's
   point set and explicit heights, optionally over a colex rank range.
+* ``oracle_consistency(A, b)`` -> whether x^A = b has solutions when
+  rank A < m: b^q = 1 for every q of a saturated basis of the left kernel
+  (Section 2, eq. ``consistency``); exact for rational or Gaussian-rational b
+  (``fractions.Fraction`` pairs), complex double otherwise.
 * ``cells_range(points, heights)`` -> the lower facets themselves (the cells of
   the regular subdivision) with their inner normals (alpha, 1), alpha exact
   rationals num / den (eq. ``lower-d-face-again``; the start data of the
@@ -33,6 +37,7 @@ import ctypes
 import os
 import subprocess
 from dataclasses import dataclass
+from fractions import Fraction
 
 import numpy as np
 
@@ -210,3 +215,44 @@ def oracle_degree(A, seed: int = 1, bits: int = 20, threads: int | None = None) 
         return dict(k=0, rank=rank, comps=comps, nvol=1, attempts=0, points=pts)
     nvol, attempts = oracle_nvol_points(pts, seed=seed, bits=bits, threads=threads)
     return dict(k=k, rank=rank, comps=comps, nvol=nvol, attempts=attempts, points=pts)
+
+
+def _cpow_exact(base, e: int):
+    """(re, im) Fraction pair raised to the integer power e (exact)."""
+    re, im = base
+    if e < 0:
+        n2 = re * re + im * im
+        re, im, e = re / n2, -im / n2, -e
+    acc = (Fraction(1), Fraction(0))
+    for _ in range(e):
+        acc = (acc[0] * re - acc[1] * im, acc[0] * im + acc[1] * re)
+    return acc
+
+
+def oracle_consistency(A, b, tol: float = 1e-9) -> dict:
+    """{consistent, residual, relations} of x^A = b (Section 2, eq.
+    ``consistency``): b^q for each q of a saturated left-kernel basis.
+
+    b: m entries, each a Python complex (evaluated in complex double) or a
+    pair (re, im) of Fractions (evaluated exactly; then residual is 0.0 or
+    the double value of the largest |b^q - 1|)."""
+    rows = [[int(x) for x in r] for r in np.asarray(A, dtype=np.int64).tolist()]
+    basis = algebra.left_kernel_basis(rows)
+    exact = all(isinstance(x, tuple) for x in b)
+    worst = 0.0
+    for q in basis:
+        if exact:
+            prod = (Fraction(1), Fraction(0))
+            for bi, qi in zip(b, q):
+                if qi:
+                    p = _cpow_exact((Fraction(bi[0]), Fraction(bi[1])), qi)
+                    prod = (prod[0] * p[0] - prod[1] * p[1], prod[0] * p[1] + prod[1] * p[0])
+            dev = abs(complex(float(prod[0] - 1), float(prod[1])))
+        else:
+            prod = complex(1.0)
+            for bi, qi in zip(b, q):
+                if qi:
+                    prod *= complex(bi) ** qi
+            dev = abs(prod - 1.0)
+        worst = max(worst, dev)
+    return dict(consistent=worst <= tol, residual=worst, relations=len(basis))

@@ -175,3 +175,16 @@ def kernel_points(A_rows, reduce: bool = True) -> tuple[int, int, list[list[int]
         P0 = lll_reduce(P0)
     pts = [[0] * k] + [[P0[i][j] for i in range(k)] for j in range(n)]
     return k, components(d), pts
+
+
+def left_kernel_basis(A_rows) -> list[list[int]]:
+    """A basis of the integer left kernel {q in Z^m : q^T A = 0} of the m x n
+    exponent matrix A (one row per binomial): the rows r..m-1 of the
+    unimodular left transform of the Smith form of A, i.e. the columns of Q_0
+    in the paper's orientation (Section 2, eq. ``rank-decomp``).  Being rows
+    of a unimodular matrix they span the whole lattice (a saturated basis)."""
+    rows = [[int(x) for x in r] for r in A_rows]
+    m, n = len(rows), len(rows[0])
+    transposed = [[rows[i][j] for i in range(m)] for j in range(n)]  # n x m
+    r, _d, Pm = smith_with_left_transform(transposed)  # Pm: m x m with Pm A Q = D
+    return [Pm[i][:] for i in range(r, m)]
