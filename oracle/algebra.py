@@ -181,10 +181,15 @@ def left_kernel_basis(A_rows) -> list[list[int]]:
     """A basis of the integer left kernel {q in Z^m : q^T A = 0} of the m x n
     exponent matrix A (one row per binomial): the rows r..m-1 of the
     unimodular left transform of the Smith form of A, i.e. the columns of Q_0
-    in the paper's orientation (Section 2, eq. ``rank-decomp``).  Being rows
-    of a unimodular matrix they span the whole lattice (a saturated basis)."""
+    in the paper's orientation (Section 2, eq. ``rank-decomp``), LLL-reduced.
+    Being rows of a unimodular matrix they span the whole lattice (a
+    saturated basis)."""
     rows = [[int(x) for x in r] for r in A_rows]
     m, n = len(rows), len(rows[0])
     transposed = [[rows[i][j] for i in range(m)] for j in range(n)]  # n x m
     r, _d, Pm = smith_with_left_transform(transposed)  # Pm: m x m with Pm A Q = D
-    return [Pm[i][:] for i in range(r, m)]
+    Q0 = [Pm[i][:] for i in range(r, m)]
+    # The condition concerns the lattice, not the basis: LLL (a unimodular
+    # change of basis) keeps it saturated and keeps the exponents of b^q small
+    # (the raw transform rows reach millions on 12 x 9 systems).
+    return lll_reduce(Q0) if len(Q0) > 1 else Q0
