@@ -195,6 +195,25 @@ int bdeg_subdivision(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int3
                      int64_t *normal_num, uint64_t *normal_den, uint64_t *n_cells, bdeg_result *out);
 
 /*
+ * Consistency of x^A = b when rank A = r < m (Section 2, eq. "consistency"
+ * and the global parametrization proposition): the system has solutions in
+ * (C*)^n exactly when b^q = prod_i b_i^{q_i} = 1 for every q of a basis of
+ * the integer left kernel {q in Z^m : q^T A = 0} (the columns of Q_0).  The
+ * basis is saturated (it spans that whole lattice, not a sublattice), as the
+ * test needs.  Host only; no device.
+ *   A           m x n row-major int64 (as for bdeg_degree);
+ *   b           m complex values as (re, im) double pairs, all nonzero;
+ *   tol         *consistent = 1 when every |b^q - 1| <= tol;
+ *   *residual   the largest |b^q - 1| (0 when r = m);
+ *   *relations  m - r, the number of basis vectors q.
+ * b^q is evaluated in double precision by repeated squaring of b_i^{|q_i|}.
+ * Errors: BDEG_E_ARG (null pointer, bad sizes, a zero b_i), BDEG_E_OVERFLOW
+ * (the host int64 algebra).
+ */
+int bdeg_consistency(const int64_t *A, int32_t m, int32_t n, const double *b, double tol,
+                     int32_t *consistent, double *residual, int32_t *relations);
+
+/*
  * Host prologue only (no device): rank, k, components and the point set
  * {0, v_1..v_n} the device would use (Euclid column elimination with a
  * pairwise-reduced saturated kernel basis).  points must hold (n+1)*n int32;

@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         "bdeg_batch_destroy": ([P], ctypes.c_int),
         "bdeg_nvol_points": ([P, P, I32, I32, U64, U64, P, P, P], ctypes.c_int),
         "bdeg_kernel_points": ([P, I32, I32, P, P, P, P], ctypes.c_int),
+        "bdeg_consistency": ([P, I32, I32, P, ctypes.c_double, P, P, P], ctypes.c_int),
         "bdeg_cells_points": ([P, P, I32, I32, U64, U64, U64, P, P, P, P, P], ctypes.c_int),
         "bdeg_subdivision": ([P, I32, I32, U64, I32, U64, P, P, P, P, P, P, P], ctypes.c_int),
         "bdeg_serve_open": ([SZ, P], ctypes.c_int),
@@ -159,6 +160,20 @@ def degree_batch(mats, seed: int = 1, lift_bits: int = 20) -> list[dict]:
     out = (Result * len(m))()
     lib().bdeg_degree_batch(cat.ctypes.data, m.ctypes.data, n.ctypes.data, len(m), seed & U64_MAX, lift_bits, out)
     return [r.as_dict() for r in out]
+
+
+def consistency(A, b, tol: float = 1e-9) -> dict:
+    """Host only: {consistent, residual, relations} of x^A = b (b: m complex values)."""
+    A = _mat(A)
+    m, n = A.shape
+    bb = np.asarray(b, dtype=np.complex128).reshape(m)
+    pairs = np.ascontiguousarray(np.stack([bb.real, bb.imag], axis=1).astype(np.float64))
+    ok, res, rel = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
+    rc = lib().bdeg_consistency(A.ctypes.data, m, n, pairs.ctypes.data, float(tol), ctypes.byref(ok),
+                                ctypes.byref(res), ctypes.byref(rel))
+    if rc != BDEG_OK:
+        raise BdegError(rc, "bdeg_consistency")
+    return dict(consistent=bool(ok.value), residual=res.value, relations=rel.value)
 
 
 def kernel_points(A) -> tuple[int, int, int, np.ndarray]:

@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <complex>
 #include <thread>
 #include <vector>
 
@@ -297,6 +298,45 @@ int bdeg_kernel_points(const int64_t *A, int32_t m, int32_t n, int32_t *k, int32
   *rank = kp.rank;
   *components = to_u128(kp.comps);
   if (!kp.pts.empty()) memcpy(points, kp.pts.data(), kp.pts.size() * sizeof(int32_t));
+  return BDEG_OK;
+}
+
+int bdeg_consistency(const int64_t *A, int32_t m, int32_t n, const double *b, double tol, int32_t *consistent,
+                     double *residual, int32_t *relations) {
+  if (!A || !b || !consistent || !residual || !relations || m < 1 || n < 1 || n > BDEG_MAX_N || m > 4096 ||
+      !(tol >= 0))
+    return BDEG_E_ARG;
+  for (int i = 0; i < m; i++)
+    if (b[2 * i] == 0.0 && b[2 * i + 1] == 0.0) return BDEG_E_ARG;
+  // left kernel of A = integer kernel of A^T (n x m)
+  std::vector<int64_t> At((size_t)n * m);
+  for (int i = 0; i < m; i++)
+    for (int j = 0; j < n; j++) At[(size_t)j * m + i] = A[(size_t)i * n + j];
+  KernelPoints kp = kernel_points(At.data(), n, m);
+  if (kp.status != BDEG_OK) return kp.status;
+  const int rel = kp.k; // m - rank
+  double worst = 0.0;
+  for (int c = 0; c < rel; c++) {
+    std::complex<double> prod(1.0, 0.0);
+    for (int i = 0; i < m; i++) {
+      const int64_t q = kp.pts[(size_t)(i + 1) * rel + c];
+      if (q == 0) continue;
+      std::complex<double> base(b[2 * i], b[2 * i + 1]);
+      if (q < 0) base = 1.0 / base;
+      uint64_t e = (uint64_t)(q < 0 ? -q : q);
+      std::complex<double> pw(1.0, 0.0);
+      while (e) {
+        if (e & 1) pw *= base;
+        base *= base;
+        e >>= 1;
+      }
+      prod *= pw;
+    }
+    worst = std::max(worst, std::abs(prod - 1.0));
+  }
+  *relations = rel;
+  *residual = worst;
+  *consistent = worst <= tol ? 1 : 0;
   return BDEG_OK;
 }
 

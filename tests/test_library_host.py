@@ -142,3 +142,54 @@ def test_work_units_cover_rank_ranges(seed):
     s, e = iv[order, 0].astype(object), iv[order, 1].astype(object)
     assert s[0] == lo and e[-1] == hi
     assert all(e[i] == s[i + 1] for i in range(len(s) - 1))
+
+
+# ------------------------------------------------------------------ consistency (host only)
+def _deficient(seed, m, n, r):
+    rng = gen.stream(0xC0C1 + seed, m * 100 + n, gen.PURPOSE_MATRIX)
+    while True:
+        B = [[rng.uniform_int(-2, 2) for _ in range(n)] for _ in range(r)]
+        C = [[rng.uniform_int(-2, 2) for _ in range(r)] for _ in range(m)]
+        A = np.array((Matrix(C) * Matrix(B)).tolist(), dtype=np.int64)
+        if Matrix(A.tolist()).rank() == r:
+            return A, rng
+
+
+@pytest.mark.parametrize("seed,m,n,r", [(0, 2, 1, 1), (1, 3, 2, 1), (2, 4, 3, 2), (3, 5, 4, 3), (4, 6, 4, 2),
+                                        (5, 8, 6, 4), (6, 7, 7, 5), (7, 12, 9, 6)])
+def test_consistency_vs_oracle(seed, m, n, r):
+    """Same decision and relation count as the oracle for images b = x0^A
+    (consistent) and for one b_i rotated by 0.5 rad (inconsistent when a
+    relation involves it)."""
+    A, rng = _deficient(seed, m, n, r)
+    angles = [rng.uniform_int(0, 10**6) / 10**6 * 2 * math.pi for _ in range(n)]
+    radii = [0.5 + rng.uniform_int(0, 1000) / 1000 for _ in range(n)]
+    x0 = [r_ * complex(math.cos(a), math.sin(a)) for r_, a in zip(radii, angles)]
+    b = [complex(np.prod([x0[j] ** int(A[i, j]) for j in range(n)])) for i in range(m)]
+    lib = bd.consistency(A, b, tol=1e-8)
+    ora = oracle.oracle_consistency(A, b, tol=1e-8)
+    assert lib["relations"] == ora["relations"] == m - r
+    assert lib["consistent"] and ora["consistent"]
+    involved = [i for i in range(m) if any(q[i] for q in algebra.left_kernel_basis(A.tolist()))]
+    for i in involved[:3]:
+        b2 = list(b)
+        b2[i] *= complex(math.cos(0.5), math.sin(0.5))
+        lib2 = bd.consistency(A, b2, tol=1e-8)
+        ora2 = oracle.oracle_consistency(A, b2, tol=1e-8)
+        assert not lib2["consistent"] and not ora2["consistent"]
+        assert lib2["residual"] > 0.1
+
+
+def test_consistency_needs_the_saturated_relation():
+    # x = b1, x = b2 with b1 = -b2: b1^2 = b2^2 holds, b1 = b2 does not
+    assert not bd.consistency([[1], [1]], [1, -1])["consistent"]
+    assert bd.consistency([[1], [1]], [1j, 1j])["consistent"]
+    assert bd.consistency([[2], [4]], [1j, -1])["consistent"]
+
+
+def test_consistency_full_rank_and_errors():
+    assert bd.consistency([[1, 2], [3, 5]], [7, 0.25]) == dict(consistent=True, residual=0.0, relations=0)
+    with pytest.raises(bd.BdegError):
+        bd.consistency([[1], [1]], [0, 1])  # a zero right-hand side is outside (C*)^m
+    with pytest.raises(bd.BdegError):
+        bd.consistency([[1], [1]], [1, 1], tol=-1.0)
