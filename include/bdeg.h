@@ -60,7 +60,7 @@ extern "C" {
                                        (Section 2, eq. "consistency"); b is not an input */
 
 #define BDEG_MAX_N 63        /* variables: N = n + 1 points fit one 64-lane wavefront */
-#define BDEG_MAX_K 12        /* kernel dimension handled on the device */
+#define BDEG_MAX_K 16        /* kernel dimension handled on the device */
 #define BDEG_MAX_ATTEMPTS 16 /* lifting draws before BDEG_E_TIE */
 
 typedef struct {
@@ -236,7 +236,7 @@ int bdeg_kernel_points(const int64_t *A, int32_t m, int32_t n, int32_t *k, int32
  *                      until bdeg_serve_close.
  *   bdeg_serve_close   finish queued work, stop the engine, free everything.
  * The budget bounds the device memory of admitted requests (a slot of about
- * 4 KiB each plus their share of the per-step work-unit buffer); requests
+ * 4.6 KiB each plus their share of the per-step work-unit buffer); requests
  * beyond it wait in arrival order.
  */
 typedef struct bdeg_server bdeg_server;

@@ -598,6 +598,7 @@ __device__ __forceinline__ void run_unit(const Tile &tl, const SysDesc &sd, cons
     break;
     BDEG_CASE(1) BDEG_CASE(2) BDEG_CASE(3) BDEG_CASE(4) BDEG_CASE(5) BDEG_CASE(6)
     BDEG_CASE(7) BDEG_CASE(8) BDEG_CASE(9) BDEG_CASE(10) BDEG_CASE(11) BDEG_CASE(12)
+    BDEG_CASE(13) BDEG_CASE(14) BDEG_CASE(15) BDEG_CASE(16)
 #undef BDEG_CASE
     default:
       break;
@@ -633,7 +634,7 @@ __device__ __forceinline__ void run_unit(const Tile &tl, const SysDesc &sd, cons
 // spills.  The single-group variant needs fewer registers (no sibling-ridge
 // path): at k = 10 it fits five waves.
 constexpr int waves_for_depth(int k, int gg) {
-  return k <= 3 ? 8 : k <= 7 ? 7 : k == 8 ? 6 : k == 9 ? 5 : k == 10 ? (gg == 1 ? 5 : 4) : k == 11 ? 4 : 3;
+  return k <= 3 ? 8 : k <= 7 ? 7 : k == 8 ? 6 : k == 9 ? 5 : k == 10 ? (gg == 1 ? 5 : 4) : k == 11 ? 4 : k <= 14 ? 3 : 2;
 }
 
 template <int KLO, int KHI, int MODE, int GG>

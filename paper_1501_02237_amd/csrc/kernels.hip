@@ -99,6 +99,10 @@ EnumFn enum_fn_9_9(int, bool);
 EnumFn enum_fn_10_10(int, bool);
 EnumFn enum_fn_11_11(int, bool);
 EnumFn enum_fn_12_12(int, bool);
+EnumFn enum_fn_13_13(int, bool);
+EnumFn enum_fn_14_14(int, bool);
+EnumFn enum_fn_15_15(int, bool);
+EnumFn enum_fn_16_16(int, bool);
 EnumFn enum_fn_1_7(int, bool);
 EnumFn enum_fn_1_12(int, bool);
 
@@ -121,6 +125,10 @@ static EnumFn enum_fn(int klo, int khi, int mode, bool single) {
       case 10: return enum_fn_10_10(mode, single);
       case 11: return enum_fn_11_11(mode, single);
       case 12: return enum_fn_12_12(mode, single);
+      case 13: return enum_fn_13_13(mode, single);
+      case 14: return enum_fn_14_14(mode, single);
+      case 15: return enum_fn_15_15(mode, single);
+      case 16: return enum_fn_16_16(mode, single);
       default: return nullptr;
     }
   }

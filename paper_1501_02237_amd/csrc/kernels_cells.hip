@@ -136,7 +136,7 @@ int launch_cell_normals(void *stream, const uint64_t *d_masks, uint64_t n, const
     break;
     BDEG_CELL_CASE(1) BDEG_CELL_CASE(2) BDEG_CELL_CASE(3) BDEG_CELL_CASE(4) BDEG_CELL_CASE(5) BDEG_CELL_CASE(6)
     BDEG_CELL_CASE(7) BDEG_CELL_CASE(8) BDEG_CELL_CASE(9) BDEG_CELL_CASE(10) BDEG_CELL_CASE(11)
-    BDEG_CELL_CASE(12)
+    BDEG_CELL_CASE(12) BDEG_CELL_CASE(13) BDEG_CELL_CASE(14) BDEG_CELL_CASE(15) BDEG_CELL_CASE(16)
 #undef BDEG_CELL_CASE
     default:
       return BDEG_E_ARG;

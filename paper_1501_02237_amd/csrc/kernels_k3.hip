@@ -1,4 +1,4 @@
-// Enumeration kernels for k = 3 (all lane-group counts, timed and counting variants).
+// Enumeration kernels for k = 3: both lane-group variants, plain, counting and
+// cell-listing modes (instantiated from enum_device.hpp).
 #include "enum_device.hpp"
-
 BDEG_ENUM_INSTANCES(3, 3)

@@ -45,6 +45,7 @@ Device *device_get(int *status) {
 }
 
 int default_waves(int kmin, int kmax, int waves_per_block) {
+  if (kmin != kmax && kmax > MIXED_K_MAX) kmin = kmax; // the deepest launch sets the grid
   int blocks = max_enum_blocks(kmin, kmax, waves_per_block, false);
   return blocks > 0 ? blocks * waves_per_block : 1024;
 }
@@ -89,9 +90,16 @@ void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t ma
 }
 
 void job_order_units(Job &job, std::vector<TileC> &tc) {
+  // k class: 0 for the mixed-k kernels, k itself above them
+  auto kclass = [&](const TileC &t) {
+    const int k = job.sys[t.t.sys].k;
+    return (job.kmin != job.kmax && k <= MIXED_K_MAX) ? 0 : k;
+  };
   std::stable_sort(tc.begin(), tc.end(), [&](const TileC &a, const TileC &b) {
     const bool ga = single_group(job.sys[a.t.sys].N), gb = single_group(job.sys[b.t.sys].N);
     if (ga != gb) return ga < gb;
+    const int ka = kclass(a), kb = kclass(b);
+    if (ka != kb) return ka < kb;
     return a.cost > b.cost;
   });
   job.tiles.resize(tc.size());
@@ -99,8 +107,17 @@ void job_order_units(Job &job, std::vector<TileC> &tc) {
   for (size_t i = 0; i < tc.size(); i++) {
     job.tiles[i] = tc[i].t;
     const bool g = single_group(job.sys[tc[i].t.sys].N);
-    if (job.granges.empty() || job.granges.back().single != g)
-      job.granges.push_back(Job::VariantRange{g, (uint32_t)i, 0});
+    const int kc = kclass(tc[i]);
+    if (job.granges.empty() || job.granges.back().single != g || job.granges.back().kclass != kc) {
+      Job::VariantRange r;
+      r.single = g;
+      r.kclass = kc;
+      r.klo = kc != 0 ? kc : job.kmin;
+      r.khi = kc != 0 ? kc : std::min(job.kmax, MIXED_K_MAX);
+      r.start = (uint32_t)i;
+      r.count = 0;
+      job.granges.push_back(r);
+    }
     job.granges.back().count++;
   }
 }
@@ -130,7 +147,7 @@ int job_upload(Job &job) {
     return rc;
   static_assert(sizeof(SysAcc) == 32, "SysAcc layout");
   if ((rc = grow(&job.d_acc, &job.cap_acc, job.sys.size()))) return rc;
-  if (!job.d_cnt && hipMalloc((void **)&job.d_cnt, GROUP_SLOTS * sizeof(DevCounters)) != hipSuccess)
+  if (!job.d_cnt && hipMalloc((void **)&job.d_cnt, MAX_RANGES * sizeof(DevCounters)) != hipSuccess)
     return BDEG_E_NOMEM;
   if (hipMemcpy(job.d_sys, job.sys.data(), job.sys.size() * sizeof(SysDesc), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(job.d_pts, job.pts.data(), job.pts.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
@@ -144,18 +161,20 @@ int job_upload(Job &job) {
 }
 
 int job_launch_pre(Job &job, hipStream_t stream) {
-  int rc = launch_clear(stream, job.d_acc, (int)job.sys.size(), job.d_cnt, GROUP_SLOTS);
+  int rc = launch_clear(stream, job.d_acc, (int)job.sys.size(), job.d_cnt, MAX_RANGES);
   if (rc) return rc;
   if (!job.explicit_heights) rc = launch_lift(stream, job.d_sys, nullptr, (int)job.sys.size(), job.d_hts);
   return rc;
 }
 
 int job_launch_enum(Job &job, hipStream_t stream) {
-  for (const Job::VariantRange &r : job.granges) {
+  if (job.granges.size() > (size_t)MAX_RANGES) return BDEG_E_STATE;
+  for (size_t i = 0; i < job.granges.size(); i++) {
+    const Job::VariantRange &r = job.granges[i];
     LaunchShape shape = job.shape;
     shape.single = r.single;
     int rc = launch_enumerate(stream, job.d_sys, job.d_pts, job.d_hts, job.d_tiles + r.start, r.count, job.d_acc,
-                              job.d_cnt + group_slot(r.single), job.kmin, job.kmax, shape);
+                              job.d_cnt + i, r.klo, r.khi, shape);
     if (rc) return rc;
   }
   return BDEG_OK;
@@ -172,7 +191,7 @@ int job_launch(Job &job, hipStream_t stream, hipEvent_t e0, hipEvent_t e1) {
 
 int job_collect(Job &job, hipStream_t stream, std::vector<SysAcc> &acc, DevCounters *cnt) {
   acc.resize(job.sys.size());
-  DevCounters blocks[GROUP_SLOTS];
+  DevCounters blocks[MAX_RANGES];
   if (!acc.empty() &&
       hipMemcpyAsync(acc.data(), job.d_acc, acc.size() * sizeof(SysAcc), hipMemcpyDeviceToHost, stream) != hipSuccess)
     return BDEG_E_DEVICE;

@@ -46,9 +46,13 @@ struct Job {
   DevCounters *d_cnt = nullptr;
   size_t cap_sys = 0, cap_pts = 0, cap_hts = 0, cap_tiles = 0, cap_acc = 0;
 
-  // units are ordered by kernel variant; one launch per variant present
+  // units are ordered by launch range: lane-group variant and k class (the
+  // mixed-k kernels cover k <= MIXED_K_MAX, deeper systems get single-k
+  // kernels); one launch, with its own counter block, per range present
   struct VariantRange {
     bool single;
+    int kclass; // 0: mixed-k kernel; else the single k
+    int klo, khi;
     uint32_t start, count;
   };
   std::vector<VariantRange> granges;
@@ -62,9 +66,12 @@ struct Job {
 void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t max_cost);
 // Order units by (kernel variant, decreasing cost) and record the variant ranges.
 void job_order_units(Job &job, std::vector<TileC> &tc);
-// index of a kernel variant among the per-launch counter blocks
+// index of a kernel variant among the per-(k, variant) counter blocks of the serving engine
 inline int group_slot(bool single) { return single ? 1 : 0; }
 constexpr int GROUP_SLOTS = 2;
+// deepest k of the mixed-k kernels; launch ranges of a job (each has a counter block)
+constexpr int MIXED_K_MAX = 12;
+constexpr int MAX_RANGES = 2 * (1 + BDEG_MAX_K - MIXED_K_MAX);
 // Upload (growing buffers as needed).
 int job_upload(Job &job);
 // Enqueue clear + lift (pre) and the enumeration; job_launch does both.

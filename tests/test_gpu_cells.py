@@ -111,6 +111,21 @@ def test_cells_match_oracle(N, k, bits):
     assert sum(int(d) for d in g.den) == v.nvol and len(g.masks) == v.cells
 
 
+@pytest.mark.parametrize("N,k,bits", [(18, 13, 16), (20, 14, 16), (21, 16, 12)])
+def test_cells_deep_k(N, k, bits):
+    """k = 13..16 with sparse point sets (few nonzero coordinates)."""
+    rng = gen.stream(0xCE9 + N, N * 100 + k, gen.PURPOSE_MATRIX)
+    while True:
+        P = [[0] * k] + [[(1 if rng.uniform_int(0, 1) else -1) if rng.uniform_int(0, 999) < 250 else 0
+                          for _ in range(k)] for _ in range(N - 1)]
+        if Matrix(P).rank() == k:
+            break
+    H = gen.random_heights(0xCEA + N + k, N, bits)
+    g = bd.cells_points(P, H)
+    o = oracle.cells_range(P, H)
+    assert g.tie == o.tie and g.as_set() == o.as_set() and len(g.masks) > 0
+
+
 @pytest.mark.parametrize("N,k", [(12, 3), (29, 4), (37, 5)])
 def test_cells_rank_slices(N, k):
     P = _points(0xCE3 + N, N, k)

@@ -49,6 +49,19 @@ def _points(seed, N, k, lo=-2, hi=2):
             return np.array(P, dtype=np.int64)
 
 
+def _sparse_points(seed, N, k, density=0.2):
+    """Points with few nonzero coordinates (in {-1, 1}), as in the master-space
+    systems: deep k stays inside the device's certified minor bound."""
+    rng = gen.stream(seed, N * 100 + k, gen.PURPOSE_MATRIX)
+    while True:
+        P = [[0] * k]
+        for _ in range(N - 1):
+            P.append([(1 if rng.uniform_int(0, 1) else -1) if rng.uniform_int(0, 999) < density * 1000 else 0
+                      for _ in range(k)])
+        if Matrix(P).rank() == k:
+            return np.array(P, dtype=np.int64)
+
+
 def _same(P, H, lo=0, hi=None):
     g = bd.nvol_points(P, H, lo, hi)
     o = oracle.nvol_range(P, H, lo, hi)
@@ -105,6 +118,17 @@ def test_ties_match_oracle(seed):
         _same(pts, H)
     P3 = np.array([[x, y, z] for x in range(2) for y in range(2) for z in range(3)], dtype=np.int64)
     _same(P3, gen.random_heights(0x7F + seed, len(P3), 3))
+
+
+@pytest.mark.parametrize("N,k,bits", [(16, 13, 16), (18, 13, 20), (17, 14, 16), (20, 14, 16), (18, 15, 12),
+                                       (19, 16, 12), (21, 16, 12), (24, 13, 16)])
+def test_nvol_points_deep_k(N, k, bits):
+    """k = 13..16 (single-k kernels beyond the mixed-k range), both lane-group
+    variants, against the oracle on identical heights."""
+    P = _sparse_points(0xDEE + N, N, k, 0.25)
+    H = gen.random_heights(0xDEF + N + k, N, bits)
+    say("deep k", N, k, bits)
+    _same(P, H)
 
 
 def test_single_candidate_and_empty_range():
@@ -181,9 +205,10 @@ def test_degree_independent_of_seed_and_width():
 
 
 def test_degree_errors():
-    with pytest.raises(bd.BdegError) as e:  # k = 14 > 12
-        bd.degree(np.zeros((1, 14), dtype=np.int64))
+    with pytest.raises(bd.BdegError) as e:  # k = 18 > BDEG_MAX_K = 16
+        bd.degree(np.zeros((1, 18), dtype=np.int64))
     assert e.value.code == bd.BDEG_E_TOO_LARGE
+    assert bd.degree(np.zeros((1, 16), dtype=np.int64))["nvol"] == 1  # k = 16: the standard simplex
     with pytest.raises(bd.BdegError) as e:
         bd.degree(np.zeros((1, 5), dtype=np.int64), lift_bits=1)
     assert e.value.code == bd.BDEG_E_ARG
@@ -199,6 +224,36 @@ def test_master_space_degrees_gpu(mk):
     assert g["comps"] == 1
     assert g["k"] == PAPER["table2_dims"][str(m)][k - 1]
     assert g["nvol"] == PAPER["table4_degrees"][mk]
+
+
+@pytest.mark.parametrize("mk", ["2,6", "3,4", "4,3", "6,2", "2,7", "7,2"])
+def test_master_space_degrees_beyond_k12(mk):
+    """Table 4 entries with k = 14 (9.4e9 candidates) and k = 16 (4.2e11
+    candidates), decided exhaustively on the device; the expected degrees are
+    the paper's printed values (beyond the oracle's reach)."""
+    m, k = map(int, mk.split(","))
+    say("master space beyond k = 12", mk)
+    g = bd.degree(gen.master_space_matrix(m, k), seed=3, lift_bits=20)
+    assert g["status"] == 0 and g["comps"] == 1
+    assert g["k"] == PAPER["table2_dims"][str(m)][k - 1] > 12
+    assert g["comps"] * g["nvol"] == PAPER["table4_degrees"][mk]
+
+
+def test_batch_mixing_deep_and_shallow_systems():
+    """One batch with k = 3..8 systems (the mixed-k kernel) and k = 13, 14
+    systems (single-k kernels, their own launch ranges) gives the single
+    results."""
+    mats = [gen.master_space_matrix(2, 6), gen.master_space_matrix(2, 1), gen.master_space_matrix(1, 5)]
+    for i in range(6):
+        mats.append(gen.quiver_matrix(0xB7, i, 14 + i, 10, 2, 3))
+    mats.append(gen.quiver_matrix(0xB8, 0, 20, 7, 1, 2))  # k = 13
+    singles = [bd.degree(A, seed=4, lift_bits=20) for A in mats]
+    assert {r["k"] for r in singles} >= {14, 13} and min(r["k"] for r in singles) <= 8
+    batch = bd.degree_batch(mats, seed=4, lift_bits=20)
+    for i, (b, s) in enumerate(zip(batch, singles)):
+        assert b["status"] == s["status"] == 0, i
+        assert (b["k"], b["comps"], b["nvol"]) == (s["k"], s["comps"], s["nvol"]), i
+    assert batch[0]["nvol"] == PAPER["table4_degrees"]["2,6"]
 
 
 # ------------------------------------------------------------------ batch
