@@ -60,7 +60,7 @@ extern "C" {
                                        (Section 2, eq. "consistency"); b is not an input */
 
 #define BDEG_MAX_N 63        /* variables: N = n + 1 points fit one 64-lane wavefront */
-#define BDEG_MAX_K 16        /* kernel dimension handled on the device */
+#define BDEG_MAX_K 18        /* kernel dimension handled on the device */
 #define BDEG_MAX_ATTEMPTS 16 /* lifting draws before BDEG_E_TIE */
 
 typedef struct {

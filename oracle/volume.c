@@ -42,7 +42,7 @@
 #define ORACLE_OK 0
 #define ORACLE_E_ARG (-1)
 #define ORACLE_E_OVERFLOW (-2)
-#define ORACLE_MAXK 18
+#define ORACLE_MAXK 20
 #define ORACLE_MAXN 64
 
 typedef __int128 i128;

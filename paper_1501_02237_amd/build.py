@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbdeg.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["algebra.cpp", "tiles.cpp", "runtime.cpp", "api.cpp", "serve.cpp", "kernels.hip",
-           "kernels_mixed12.hip", "kernels_mixed7.hip", "kernels_cells.hip"] + [f"kernels_k{k}.hip" for k in range(16, 0, -1)]
+           "kernels_mixed12.hip", "kernels_mixed7.hip", "kernels_cells.hip"] + [f"kernels_k{k}.hip" for k in range(18, 0, -1)]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

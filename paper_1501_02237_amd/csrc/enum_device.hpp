@@ -598,7 +598,7 @@ __device__ __forceinline__ void run_unit(const Tile &tl, const SysDesc &sd, cons
     break;
     BDEG_CASE(1) BDEG_CASE(2) BDEG_CASE(3) BDEG_CASE(4) BDEG_CASE(5) BDEG_CASE(6)
     BDEG_CASE(7) BDEG_CASE(8) BDEG_CASE(9) BDEG_CASE(10) BDEG_CASE(11) BDEG_CASE(12)
-    BDEG_CASE(13) BDEG_CASE(14) BDEG_CASE(15) BDEG_CASE(16)
+    BDEG_CASE(13) BDEG_CASE(14) BDEG_CASE(15) BDEG_CASE(16) BDEG_CASE(17) BDEG_CASE(18)
 #undef BDEG_CASE
     default:
       break;

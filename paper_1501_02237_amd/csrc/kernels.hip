@@ -103,6 +103,8 @@ EnumFn enum_fn_13_13(int, bool);
 EnumFn enum_fn_14_14(int, bool);
 EnumFn enum_fn_15_15(int, bool);
 EnumFn enum_fn_16_16(int, bool);
+EnumFn enum_fn_17_17(int, bool);
+EnumFn enum_fn_18_18(int, bool);
 EnumFn enum_fn_1_7(int, bool);
 EnumFn enum_fn_1_12(int, bool);
 
@@ -129,6 +131,8 @@ static EnumFn enum_fn(int klo, int khi, int mode, bool single) {
       case 14: return enum_fn_14_14(mode, single);
       case 15: return enum_fn_15_15(mode, single);
       case 16: return enum_fn_16_16(mode, single);
+      case 17: return enum_fn_17_17(mode, single);
+      case 18: return enum_fn_18_18(mode, single);
       default: return nullptr;
     }
   }

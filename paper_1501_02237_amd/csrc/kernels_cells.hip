@@ -10,7 +10,8 @@
 // num = sign(n_k) n_{0..k-1} and den = |n_k|, the cell's normalized volume.
 //
 // One thread per cell (cells are few next to the candidates; this pass is a
-// small fraction of the enumeration).  Fraction-free (Bareiss) elimination of X
+// small fraction of the enumeration); unrolled per k up to 12, a runtime-k
+// version above.  Fraction-free (Bareiss) elimination of X
 // with row pivoting on the spatial columns leaves an upper-triangular U whose
 // last pivot is det M up to the sign of the row permutation; taking
 // n_k = U[k-1][k-1], back substitution
@@ -117,6 +118,102 @@ __global__ void __launch_bounds__(256) cell_normals_kernel(const uint64_t *__res
   if (bad) atomicOr(err, CELL_ERR_RANGE);
 }
 
+// The same for k > 12 with the dimension read at run time (loops instead of
+// unrolled code; the matrix lives in private memory).  Cells of such systems
+// are few next to their candidates, and unrolled instances this deep take
+// minutes to compile.
+constexpr int DEEP_K_MAX = BDEG_MAX_K;
+__global__ void __launch_bounds__(256) cell_normals_deep_kernel(const uint64_t *__restrict__ masks, uint64_t n,
+                                                                const int32_t *__restrict__ pts,
+                                                                const int64_t *__restrict__ hts, int N, int K,
+                                                                int64_t *__restrict__ num,
+                                                                uint64_t *__restrict__ den,
+                                                                uint32_t *__restrict__ err) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t m = masks[i];
+  const uint64_t allowed = N >= 64 ? ~0ull : ((1ull << N) - 1);
+  if (K < 1 || K > DEEP_K_MAX || __builtin_popcountll(m) != K + 1 || (m & ~allowed)) {
+    atomicOr(err, CELL_ERR_MASK);
+    return;
+  }
+  const int c0 = __builtin_ctzll(m);
+  m &= m - 1;
+  int32_t a[DEEP_K_MAX][DEEP_K_MAX];
+  int64_t h[DEEP_K_MAX];
+#pragma unroll 1
+  for (int r = 0; r < K; r++) {
+    const int c = __builtin_ctzll(m);
+    m &= m - 1;
+#pragma unroll 1
+    for (int q = 0; q < K; q++) a[r][q] = pts[c * K + q] - pts[c0 * K + q];
+    h[r] = hts[c] - hts[c0];
+  }
+  bool bad = false;
+  int32_t prev = 1;
+#pragma unroll 1
+  for (int t = 0; t < K; t++) {
+    int p = t;
+    while (p < K && a[p][t] == 0) p++;
+    if (p == K) {
+      bad = true; // D = 0: not a cell
+      break;
+    }
+    if (p != t) {
+#pragma unroll 1
+      for (int q = t; q < K; q++) {
+        const int32_t x = a[t][q];
+        a[t][q] = a[p][q];
+        a[p][q] = x;
+      }
+      const int64_t x = h[t];
+      h[t] = h[p];
+      h[p] = x;
+    }
+    const int32_t piv = a[t][t];
+    const Div dv = make_div(prev);
+#pragma unroll 1
+    for (int r = t + 1; r < K; r++) {
+      const int32_t art = a[r][t];
+#pragma unroll 1
+      for (int q = t + 1; q < K; q++) {
+        const int64_t v = (int64_t)piv * a[r][q] - (int64_t)art * a[t][q];
+        const int32_t w = exdiv32(v, dv);
+        bad |= (int64_t)w * prev != v;
+        a[r][q] = w;
+      }
+      const __int128 v = (__int128)piv * h[r] - (__int128)art * h[t];
+      const int64_t w = exdiv128(v, dv);
+      bad |= (__int128)w * prev != v;
+      h[r] = w;
+    }
+    prev = piv;
+  }
+  int64_t nv[DEEP_K_MAX + 1];
+  if (!bad) {
+    nv[K] = a[K - 1][K - 1];
+#pragma unroll 1
+    for (int r = K - 1; r >= 0; r--) {
+      __int128 s = (__int128)h[r] * nv[K];
+#pragma unroll 1
+      for (int j = r + 1; j < K; j++) s += (__int128)a[r][j] * nv[j];
+      const int32_t d = a[r][r];
+      const int64_t w = exdiv128(-s, make_div(d));
+      bad |= (__int128)w * d != -s;
+      nv[r] = w;
+    }
+  }
+  if (bad) {
+    atomicOr(err, CELL_ERR_RANGE);
+    return;
+  }
+  const int64_t nk = nv[K];
+  const bool flip = nk < 0;
+#pragma unroll 1
+  for (int q = 0; q < K; q++) num[i * K + q] = flip ? -nv[q] : nv[q];
+  den[i] = (uint64_t)(flip ? -nk : nk);
+}
+
 } // namespace dev
 
 int launch_cell_normals(void *stream, const uint64_t *d_masks, uint64_t n, const int32_t *d_pts,
@@ -136,10 +233,12 @@ int launch_cell_normals(void *stream, const uint64_t *d_masks, uint64_t n, const
     break;
     BDEG_CELL_CASE(1) BDEG_CELL_CASE(2) BDEG_CELL_CASE(3) BDEG_CELL_CASE(4) BDEG_CELL_CASE(5) BDEG_CELL_CASE(6)
     BDEG_CELL_CASE(7) BDEG_CELL_CASE(8) BDEG_CELL_CASE(9) BDEG_CELL_CASE(10) BDEG_CELL_CASE(11)
-    BDEG_CELL_CASE(12) BDEG_CELL_CASE(13) BDEG_CELL_CASE(14) BDEG_CELL_CASE(15) BDEG_CELL_CASE(16)
+    BDEG_CELL_CASE(12)
 #undef BDEG_CELL_CASE
     default:
-      return BDEG_E_ARG;
+      hipLaunchKernelGGL(dev::cell_normals_deep_kernel, grid, block, 0, s, d_masks, n, d_pts, d_hts, N, k, d_num,
+                         d_den, d_err);
+      break;
   }
   return hipGetLastError() == hipSuccess ? BDEG_OK : BDEG_E_DEVICE;
 }

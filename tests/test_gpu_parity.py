@@ -205,10 +205,10 @@ def test_degree_independent_of_seed_and_width():
 
 
 def test_degree_errors():
-    with pytest.raises(bd.BdegError) as e:  # k = 18 > BDEG_MAX_K = 16
-        bd.degree(np.zeros((1, 18), dtype=np.int64))
+    with pytest.raises(bd.BdegError) as e:  # k = 19 > BDEG_MAX_K = 18
+        bd.degree(np.zeros((1, 19), dtype=np.int64))
     assert e.value.code == bd.BDEG_E_TOO_LARGE
-    assert bd.degree(np.zeros((1, 16), dtype=np.int64))["nvol"] == 1  # k = 16: the standard simplex
+    assert bd.degree(np.zeros((1, 18), dtype=np.int64))["nvol"] == 1  # k = 18: the standard simplex
     with pytest.raises(bd.BdegError) as e:
         bd.degree(np.zeros((1, 5), dtype=np.int64), lift_bits=1)
     assert e.value.code == bd.BDEG_E_ARG
@@ -226,11 +226,12 @@ def test_master_space_degrees_gpu(mk):
     assert g["nvol"] == PAPER["table4_degrees"][mk]
 
 
-@pytest.mark.parametrize("mk", ["2,6", "3,4", "4,3", "6,2", "2,7", "7,2"])
+@pytest.mark.parametrize("mk", ["2,6", "3,4", "4,3", "6,2", "2,7", "7,2", "3,5"])
 def test_master_space_degrees_beyond_k12(mk):
-    """Table 4 entries with k = 14 (9.4e9 candidates) and k = 16 (4.2e11
-    candidates), decided exhaustively on the device; the expected degrees are
-    the paper's printed values (beyond the oracle's reach)."""
+    """Table 4 entries with k = 14 (9.4e9 candidates), k = 16 (4.2e11) and
+    k = 17 (2.8e12, about 75 s), decided exhaustively on the device; the
+    expected degrees are the paper's printed values (beyond the oracle's
+    reach)."""
     m, k = map(int, mk.split(","))
     say("master space beyond k = 12", mk)
     g = bd.degree(gen.master_space_matrix(m, k), seed=3, lift_bits=20)
