@@ -195,6 +195,39 @@ int bdeg_subdivision(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int3
                      int64_t *normal_num, uint64_t *normal_den, uint64_t *n_cells, bdeg_result *out);
 
 /*
+ * The regular subdivision by simplicial pivoting (Section 4.2-4.4): instead
+ * of deciding every (k+1)-subset, walk from one cell to its neighbours across
+ * facets (for the facet opposite v, the new vertex minimizes the height above
+ * the cell's hyperplane over the distance beyond the facet), keeping a device
+ * hash set of visited cells.  The work follows the number of cells, so k up
+ * to BDEG_PIVOT_MAX_K and N up to 64 are in reach when the cells are few.
+ *   points, heights  as for bdeg_nvol_points (k <= BDEG_PIVOT_MAX_K);
+ *   start_mask       a cell (k+1 points) that is a lower facet for `heights`;
+ *                    BDEG_E_ARG when it is not;
+ *   cell_masks [cap] the cells in discovery order (cap = 0: none copied);
+ *   *n_cells, *nvol  number of cells and the sum of their normalized volumes;
+ *   *tie             a non-generic lower face was met (results then invalid).
+ * Device memory grows with the number of cells (16 bytes per cell in flight,
+ * doubled on demand); BDEG_E_NOMEM beyond 2^31 cells.
+ */
+#define BDEG_PIVOT_MAX_K 24
+int bdeg_pivot_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k,
+                      uint64_t start_mask, uint64_t cap, uint64_t *cell_masks, uint64_t *n_cells,
+                      bdeg_u128 *nvol, int32_t *tie);
+
+/*
+ * Degree data of x^A = b (as bdeg_degree) computed by the cell walk, for k up
+ * to BDEG_PIVOT_MAX_K.  The lifting gives height 0 to a greedy affinely
+ * independent set of k+1 points (point 0 first, then in index order) and
+ * 1 + a seeded draw in [0, 2^lift_bits) to the others, so that set is a lower
+ * facet to start from; a tie redraws the other heights (at most
+ * BDEG_MAX_ATTEMPTS draws).  nvol is the same as bdeg_degree's (it does not
+ * depend on the lifting); cells counts this lifting's cells.
+ */
+int bdeg_degree_pivot(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int32_t lift_bits,
+                      bdeg_result *out);
+
+/*
  * Consistency of x^A = b when rank A = r < m (Section 2, eq. "consistency"
  * and the global parametrization proposition): the system has solutions in
  * (C*)^n exactly when b^q = prod_i b_i^{q_i} = 1 for every q of a basis of

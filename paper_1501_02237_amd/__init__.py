@@ -95,6 +95,8 @@ def lib() -> ctypes.CDLL:
         "bdeg_nvol_points": ([P, P, I32, I32, U64, U64, P, P, P], ctypes.c_int),
         "bdeg_kernel_points": ([P, I32, I32, P, P, P, P], ctypes.c_int),
         "bdeg_consistency": ([P, I32, I32, P, ctypes.c_double, P, P, P], ctypes.c_int),
+        "bdeg_pivot_points": ([P, P, I32, I32, U64, U64, P, P, P, P], ctypes.c_int),
+        "bdeg_degree_pivot": ([P, I32, I32, U64, I32, P], ctypes.c_int),
         "bdeg_cells_points": ([P, P, I32, I32, U64, U64, U64, P, P, P, P, P], ctypes.c_int),
         "bdeg_subdivision": ([P, I32, I32, U64, I32, U64, P, P, P, P, P, P, P], ctypes.c_int),
         "bdeg_serve_open": ([SZ, P], ctypes.c_int),
@@ -153,6 +155,32 @@ def _pack(mats):
     n = np.array([A.shape[1] for A in mats], dtype=np.int32)
     cat = np.ascontiguousarray(np.concatenate([A.ravel() for A in mats]).astype(np.int64))
     return cat, m, n
+
+
+def degree_pivot(A, seed: int = 1, lift_bits: int = 20, check: bool = True) -> dict:
+    """Degree data of x^A = b computed by the cell walk (simplicial pivoting), k <= 24."""
+    A = _mat(A)
+    r = Result()
+    rc = lib().bdeg_degree_pivot(A.ctypes.data, A.shape[0], A.shape[1], seed & U64_MAX, lift_bits, ctypes.byref(r))
+    if check and rc != BDEG_OK:
+        raise BdegError(rc, "bdeg_degree_pivot")
+    d = r.as_dict()
+    d["status"] = rc if rc != BDEG_OK else d["status"]
+    return d
+
+
+def pivot_points(points, heights, start_mask: int, cap: int = 0) -> dict:
+    """The cell walk from a caller's start cell: {nvol, cells, tie, masks}."""
+    P = np.ascontiguousarray(np.asarray(points, dtype=np.int32))
+    H = np.ascontiguousarray(np.asarray(heights, dtype=np.int64))
+    N, k = P.shape
+    masks = np.zeros(max(cap, 1), dtype=np.uint64)
+    n, nv, tie = ctypes.c_uint64(), U128(), ctypes.c_int32()
+    rc = lib().bdeg_pivot_points(P.ctypes.data, H.ctypes.data, N, k, int(start_mask) & U64_MAX, cap,
+                                 masks.ctypes.data, ctypes.byref(n), ctypes.byref(nv), ctypes.byref(tie))
+    if rc != BDEG_OK:
+        raise BdegError(rc, "bdeg_pivot_points")
+    return dict(nvol=nv.value, cells=n.value, tie=bool(tie.value), masks=masks[: min(cap, n.value)].copy())
 
 
 def degree_batch(mats, seed: int = 1, lift_bits: int = 20) -> list[dict]:

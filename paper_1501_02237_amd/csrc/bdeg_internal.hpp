@@ -97,6 +97,39 @@ struct CellSink {
   uint64_t *count;
 };
 
+// ------------------------------------------------------------ cell walk (kernels_pivot*.hip)
+constexpr int PIVOT_MAX_K = BDEG_PIVOT_MAX_K; // deepest k of the cell walk
+constexpr uint32_t PIVOT_TIE = 1;       // a non-generic lower face was met
+constexpr uint32_t PIVOT_ERR_FULL = 2;  // hash set or work list out of room
+constexpr uint32_t PIVOT_ERR_STATE = 4; // a listed cell is not a lower facet (bad start cell)
+
+struct PivotCounters {
+  uint32_t next;  // work item head of the current level
+  uint32_t tail;  // cells in the work list
+  uint32_t flags; // PIVOT_*
+  uint32_t pad;
+  unsigned long long vol_lo, vol_hi; // sum of |D| over processed cells (128-bit)
+  unsigned long long cells;          // processed cells
+};
+
+struct PivotArgs {
+  const int32_t *pts; // N x k
+  const int64_t *hts; // N
+  int N;
+  uint64_t *list;     // work list of cells (vertex masks), in discovery order
+  uint32_t first;     // this level's cells are list[first, first + count)
+  uint32_t count;
+  uint32_t cap_list;
+  uint64_t *table;    // hash set of cells (0 = empty), power-of-two size
+  uint64_t table_mask;
+  PivotCounters *cnt;
+};
+typedef void (*PivotFn)(PivotArgs);
+// One level of the walk: every cell of [first, first + count) is processed by
+// one wavefront of a persistent grid of `blocks` blocks of 4 wavefronts.
+int launch_pivot(void *stream, const PivotArgs &a, int k, int blocks);
+int max_pivot_blocks(int k);
+
 // ------------------------------------------------------------ kernels (kernels.hip)
 // enumeration kernel variants
 constexpr int MODE_PLAIN = 0; // volume, cell count and tie flag

@@ -1,0 +1,269 @@
+// Host side of the cell walk (simplicial pivoting, paper Section 4.2-4.4):
+// device buffers, the level-by-level launch loop and the C-ABI entry points.
+//
+// The walk starts from a cell that is a lower facet for the given heights and
+// visits the cells breadth-first: every level is one persistent launch over
+// the cells discovered by the previous level; the host reads the work-list
+// length between levels (no device-side waiting).  A full hash set or work
+// list doubles both and restarts; a tie is returned to the caller.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "api_internal.hpp"
+#include "runtime.hpp"
+
+namespace bdeg {
+namespace {
+
+uint64_t host_cell_hash(uint64_t m) { // same mixing as the device hash set
+  m ^= m >> 33;
+  m *= 0xFF51AFD7ED558CCDull;
+  m ^= m >> 33;
+  m *= 0xC4CEB9FE1A85EC53ull;
+  m ^= m >> 33;
+  return m;
+}
+
+struct WalkBuffers {
+  int32_t *pts = nullptr;
+  int64_t *hts = nullptr;
+  uint64_t *list = nullptr, *table = nullptr;
+  PivotCounters *cnt = nullptr;
+  uint64_t cap = 0; // cells (work list and hash set; the set has 2 * cap slots)
+  void release() {
+    for (void *p : {(void *)pts, (void *)hts, (void *)list, (void *)table, (void *)cnt})
+      if (p) (void)hipFree(p);
+    pts = nullptr;
+    hts = nullptr;
+    list = table = nullptr;
+    cnt = nullptr;
+    cap = 0;
+  }
+  ~WalkBuffers() { release(); }
+};
+
+struct WalkResult {
+  u128 nvol = 0;
+  uint64_t cells = 0;
+  bool tie = false;
+};
+
+// One walk from `start`; BDEG_E_NOMEM when the device cannot hold the cells.
+int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k, uint64_t start,
+         std::vector<uint64_t> *cells_out, WalkResult &out) {
+  WalkBuffers b;
+  if (hipMalloc((void **)&b.pts, (size_t)N * k * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc((void **)&b.hts, (size_t)N * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc((void **)&b.cnt, sizeof(PivotCounters)) != hipSuccess)
+    return BDEG_E_NOMEM;
+  if (hipMemcpy(b.pts, points, (size_t)N * k * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b.hts, heights, (size_t)N * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
+    return BDEG_E_DEVICE;
+  const int blocks = max_pivot_blocks(k);
+  if (blocks <= 0) return BDEG_E_DEVICE;
+  for (uint64_t cap = 1ull << 20;; cap *= 2) {
+    if (cap > (1ull << 31)) return BDEG_E_NOMEM; // work-list indices are 32-bit
+    if (b.list) (void)hipFree(b.list);
+    if (b.table) (void)hipFree(b.table);
+    b.list = b.table = nullptr;
+    if (hipMalloc((void **)&b.list, cap * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc((void **)&b.table, 2 * cap * sizeof(uint64_t)) != hipSuccess)
+      return BDEG_E_NOMEM;
+    b.cap = cap;
+    const uint64_t tmask = 2 * cap - 1;
+    PivotCounters c0{};
+    c0.tail = 1;
+    if (hipMemsetAsync(b.table, 0, 2 * cap * sizeof(uint64_t), D->stream) != hipSuccess ||
+        hipMemcpyAsync(b.list, &start, sizeof start, hipMemcpyHostToDevice, D->stream) != hipSuccess ||
+        hipMemcpyAsync(b.table + (host_cell_hash(start) & tmask), &start, sizeof start, hipMemcpyHostToDevice,
+                       D->stream) != hipSuccess ||
+        hipMemcpyAsync(b.cnt, &c0, sizeof c0, hipMemcpyHostToDevice, D->stream) != hipSuccess)
+      return BDEG_E_DEVICE;
+    PivotArgs a;
+    a.pts = b.pts;
+    a.hts = b.hts;
+    a.N = N;
+    a.list = b.list;
+    a.cap_list = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull);
+    a.table = b.table;
+    a.table_mask = tmask;
+    a.cnt = b.cnt;
+    uint32_t first = 0, count = 1;
+    PivotCounters c{};
+    bool regrow = false;
+    while (count > 0) {
+      a.first = first;
+      a.count = count;
+      const uint32_t zero = 0;
+      if (hipMemcpyAsync(&b.cnt->next, &zero, sizeof zero, hipMemcpyHostToDevice, D->stream) != hipSuccess)
+        return BDEG_E_DEVICE;
+      int rc = launch_pivot(D->stream, a, k, blocks);
+      if (rc) return rc;
+      if (hipMemcpyAsync(&c, b.cnt, sizeof c, hipMemcpyDeviceToHost, D->stream) != hipSuccess ||
+          hipStreamSynchronize(D->stream) != hipSuccess)
+        return BDEG_E_DEVICE;
+      if (c.flags & PIVOT_ERR_STATE) return BDEG_E_ARG; // the start is not a lower facet
+      if (c.flags & PIVOT_ERR_FULL) {
+        regrow = true;
+        break;
+      }
+      if (c.flags & PIVOT_TIE) {
+        out.tie = true;
+        return BDEG_OK;
+      }
+      first += count;
+      count = c.tail - first;
+    }
+    if (regrow) continue;
+    out.tie = false;
+    out.nvol = ((u128)c.vol_hi << 64) | c.vol_lo;
+    out.cells = c.cells;
+    if (cells_out) {
+      cells_out->resize(c.tail);
+      if (c.tail && hipMemcpy(cells_out->data(), b.list, c.tail * sizeof(uint64_t), hipMemcpyDeviceToHost) !=
+                        hipSuccess)
+        return BDEG_E_DEVICE;
+    }
+    return BDEG_OK;
+  }
+}
+
+// A start cell: point 0 and, in index order, every point that raises the
+// affine rank (fraction-free elimination of the difference rows, int128 with
+// overflow checks).  0 when the points do not span Z^k.
+uint64_t greedy_simplex(const int32_t *pts, int N, int k) {
+  std::vector<std::vector<__int128>> rows; // echelon rows, pivot column of row i is piv[i]
+  std::vector<int> piv;
+  std::vector<__int128> prevs;
+  uint64_t mask = 1;
+  for (int j = 1; j < N && (int)rows.size() < k; j++) {
+    std::vector<__int128> r(k);
+    for (int i = 0; i < k; i++) r[i] = (__int128)pts[(size_t)j * k + i] - pts[i];
+    // reduce against the echelon rows: r <- (p_t r - r[c_t] row_t) / p_{t-1}
+    __int128 prev = 1;
+    bool ok = true;
+    for (size_t t = 0; t < rows.size() && ok; t++) {
+      const int c = piv[t];
+      const __int128 p = rows[t][c], f = r[c];
+      for (int i = 0; i < k; i++) {
+        __int128 u, v, w;
+        if (__builtin_mul_overflow(p, r[i], &u) || __builtin_mul_overflow(f, rows[t][i], &v) ||
+            __builtin_sub_overflow(u, v, &w)) {
+          ok = false;
+          break;
+        }
+        r[i] = w / prev;
+      }
+      prev = p;
+    }
+    if (!ok) return 0;
+    int c = -1;
+    for (int i = 0; i < k; i++)
+      if (r[i] != 0) {
+        c = i;
+        break;
+      }
+    if (c < 0) continue; // affinely dependent on the chosen points
+    rows.push_back(r);
+    piv.push_back(c);
+    prevs.push_back(prev);
+    mask |= 1ull << j;
+  }
+  return (int)rows.size() == k ? mask : 0;
+}
+
+// Heights of the walk: 0 on the start cell, 1 + a counter-based draw in
+// [0, 2^bits) elsewhere, so the start cell is a lower facet.
+void walk_heights(uint64_t start, int N, uint64_t key, int bits, std::vector<int64_t> &h) {
+  h.assign(N, 0);
+  for (int j = 0; j < N; j++) {
+    if ((start >> j) & 1) continue;
+    uint64_t z = key + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    h[j] = 1 + (int64_t)(z >> (64 - bits));
+  }
+}
+
+bdeg_u128 u128_out(u128 v) { return bdeg_u128{(uint64_t)v, (uint64_t)(v >> 64)}; }
+
+} // namespace
+} // namespace bdeg
+
+using namespace bdeg;
+
+extern "C" {
+
+int bdeg_pivot_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, uint64_t start_mask,
+                      uint64_t cap, uint64_t *cell_masks, uint64_t *n_cells, bdeg_u128 *nvol, int32_t *tie) {
+  if (!points || !heights || !n_cells || !nvol || !tie || k < 1 || k > PIVOT_MAX_K || N < k + 1 || N > 64 ||
+      (cap > 0 && !cell_masks))
+    return BDEG_E_ARG;
+  if (__builtin_popcountll(start_mask) != k + 1 || (N < 64 && (start_mask >> N) != 0)) return BDEG_E_ARG;
+  int64_t hmin = heights[0], hmax = heights[0];
+  for (int j = 0; j < N; j++) {
+    if (heights[j] >= (1ll << 40) || heights[j] <= -(1ll << 40)) return BDEG_E_ARG;
+    hmin = std::min(hmin, heights[j]);
+    hmax = std::max(hmax, heights[j]);
+  }
+  if (!device_bounds_ok(points, N, k, (uint64_t)(hmax - hmin))) return BDEG_E_OVERFLOW;
+  int st;
+  Device *D = device_get(&st);
+  if (!D) return st;
+  std::lock_guard<std::mutex> lk(D->mu);
+  std::vector<uint64_t> cells;
+  WalkResult r;
+  int rc = walk(D, points, heights, N, k, start_mask, cap > 0 ? &cells : nullptr, r);
+  if (rc) return rc;
+  *tie = r.tie ? 1 : 0;
+  *nvol = u128_out(r.nvol);
+  *n_cells = r.cells;
+  if (cap > 0 && !r.tie) memcpy(cell_masks, cells.data(), std::min<uint64_t>(cap, cells.size()) * sizeof(uint64_t));
+  return BDEG_OK;
+}
+
+int bdeg_degree_pivot(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int32_t lift_bits, bdeg_result *out) {
+  if (!A || !out) return BDEG_E_ARG;
+  memset(out, 0, sizeof *out);
+  if (m < 1 || n < 1 || n > BDEG_MAX_N || lift_bits < 2 || lift_bits > 30) return out->status = BDEG_E_ARG;
+  KernelPoints kp = kernel_points(A, m, n);
+  if (kp.status != BDEG_OK) return out->status = kp.status;
+  out->k = kp.k;
+  out->rank = kp.rank;
+  out->flags = kp.flags;
+  out->components = u128_out(kp.comps);
+  if (kp.k == 0) {
+    out->nvol = bdeg_u128{1, 0};
+    return out->status = BDEG_OK;
+  }
+  const int N = n + 1, k = kp.k;
+  if (k > PIVOT_MAX_K) return out->status = BDEG_E_TOO_LARGE;
+  out->candidates = binom_u64(N, k + 1);
+  if (!device_bounds_ok(kp.pts.data(), N, k, (1ull << lift_bits) + 1)) return out->status = BDEG_E_OVERFLOW;
+  const uint64_t start = greedy_simplex(kp.pts.data(), N, k);
+  if (!start) return out->status = BDEG_E_OVERFLOW; // the int128 rank test overflowed
+  int st;
+  Device *D = device_get(&st);
+  if (!D) return out->status = st;
+  std::lock_guard<std::mutex> lk(D->mu);
+  std::vector<int64_t> h;
+  for (int attempt = 0; attempt < BDEG_MAX_ATTEMPTS; attempt++) {
+    walk_heights(start, N, lift_key(seed, 0, (uint32_t)attempt) ^ 0x5049564F54ull, lift_bits, h);
+    WalkResult r;
+    int rc = walk(D, kp.pts.data(), h.data(), N, k, start, nullptr, r);
+    out->attempts = attempt + 1;
+    if (rc) return out->status = rc;
+    if (r.tie) continue;
+    out->nvol = u128_out(r.nvol);
+    out->cells = r.cells;
+    return out->status = BDEG_OK;
+  }
+  return out->status = BDEG_E_TIE;
+}
+
+} // extern "C"

@@ -1,0 +1,125 @@
+"""Parity of the cell walk (simplicial pivoting, Section 4.2-4.4) with the oracle.
+
+The walk visits the cells of the regular subdivision across their facets
+from one start cell.  For a given lifting the cells are unique, so the walk's
+cell set must equal the oracle's lower facets bit for bit, and the volumes
+must agree.  The tests build their own start cell and heights (height 0 on an
+affinely independent set, so that set is a lower facet; positive seeded
+heights elsewhere), independently of the library's construction.  At sizes
+beyond the oracle the expected values are the exhaustive device path's and
+the paper's Table 4.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from sympy import Matrix
+
+import gen
+import oracle
+import paper_1501_02237_amd as bd
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+PAPER = json.load(open(os.path.join(GOLD, "paper_values.json")))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    say("gpu fixture: importing torch")
+    import torch
+
+    assert torch.cuda.is_available(), "gpu tests need a GPU"
+    oracle.build(force=False)
+    bd.lib()
+
+
+def _independent_set(P):
+    """Point 0 and, scanning backwards from the last point, each point that
+    raises the affine rank (sympy ranks)."""
+    k = len(P[0])
+    chosen = [0]
+    for j in range(len(P) - 1, 0, -1):
+        M = Matrix([[P[c][q] - P[0][q] for q in range(k)] for c in chosen[1:] + [j]])
+        if M.rank() == len(chosen):
+            chosen.append(j)
+        if len(chosen) == k + 1:
+            break
+    return chosen
+
+
+def _lifting(P, seed, bits):
+    start = _independent_set(P)
+    r = gen.random_heights(seed, len(P), bits)
+    H = np.array([0 if j in start else 1 + int(r[j]) for j in range(len(P))], dtype=np.int64)
+    return sum(1 << j for j in start), H
+
+
+def _points(seed, N, k, lo=-2, hi=2):
+    if k >= 7:
+        lo, hi = max(lo, -1), min(hi, 1)
+    rng = gen.stream(seed, N * 100 + k, gen.PURPOSE_MATRIX)
+    while True:
+        P = [[0] * k] + [[rng.uniform_int(lo, hi) for _ in range(k)] for _ in range(N - 1)]
+        if Matrix(P).rank() == k:
+            return P
+
+
+@pytest.mark.parametrize("N,k,bits", [(5, 1, 12), (8, 2, 16), (12, 3, 16), (16, 4, 20), (20, 5, 20), (24, 6, 20),
+                                       (33, 4, 20), (40, 3, 20), (18, 8, 16), (16, 10, 16), (64, 2, 24)])
+def test_walk_matches_oracle_cells(N, k, bits):
+    P = _points(0x9A1 + N, N, k)
+    start, H = _lifting(P, 0x9A2 + N * 7 + k, bits)
+    say("walk", N, k, bits)
+    g = bd.pivot_points(P, H, start, cap=1 << 20)
+    o = oracle.cells_range(P, H)
+    assert g["tie"] == o.tie
+    if not o.tie:
+        assert {int(m) for m in g["masks"]} == {int(m) for m in o.masks}
+        assert g["cells"] == len(o.masks)
+        assert g["nvol"] == sum(int(d) for d in o.den)
+
+
+def test_walk_rejects_a_start_that_is_not_a_lower_facet():
+    P = _points(0x9A3, 12, 3)
+    start, H = _lifting(P, 0x9A4, 16)
+    H = H.copy()
+    H[[j for j in range(12) if (start >> j) & 1][0]] += 1 << 24  # lift one start vertex far up
+    with pytest.raises(bd.BdegError) as e:
+        bd.pivot_points(P, H, start)
+    assert e.value.code == bd.BDEG_E_ARG
+
+
+@pytest.mark.parametrize("idx", range(6))
+def test_degree_pivot_equals_exhaustive(idx):
+    rng = gen.stream(0x9A5, idx, gen.PURPOSE_SIZES)
+    n = rng.uniform_int(10, 26)
+    k = rng.uniform_int(2, 8)
+    A = gen.quiver_matrix(0x9A6, idx, n, n - k, 2, 3)
+    say("pivot vs exhaustive", n, k)
+    p = bd.degree_pivot(A, seed=2)
+    e = bd.degree(A, seed=2)
+    assert (p["k"], p["comps"], p["nvol"]) == (e["k"], e["comps"], e["nvol"])
+
+
+def test_degree_pivot_golden_systems():
+    for name, s in (("cfg1", gen.cfg1_system()), ("cfg2", gen.cfg2_system()), ("cfg4", gen.cfg4_system())):
+        gold = json.load(open(os.path.join(GOLD, f"{name}_expected.json")))["systems"][0]
+        r = bd.degree_pivot(s.A, seed=1, lift_bits=s.lift_bits)
+        say(name, r["nvol"], r["cells"])
+        assert (r["k"], r["comps"], r["nvol"]) == (gold["k"], gold["comps"], gold["nvol"])
+
+
+@pytest.mark.parametrize("mk", sorted(PAPER["table4_degrees"], key=lambda s: tuple(map(int, s.split(",")))))
+def test_degree_pivot_table4(mk):
+    """Every degree of the paper's Table 4 by the cell walk, up to W_{4,5} and
+    W_{5,4} (k = 22, about 5e7 cells), beyond the exhaustive path's k <= 18."""
+    m, k = map(int, mk.split(","))
+    say("table 4 by pivoting", mk)
+    r = bd.degree_pivot(gen.master_space_matrix(m, k), seed=5, lift_bits=20)
+    assert r["status"] == 0 and r["comps"] * r["nvol"] == PAPER["table4_degrees"][mk]
