@@ -129,6 +129,8 @@ typedef void (*PivotFn)(PivotArgs);
 // one wavefront of a persistent grid of `blocks` blocks of 4 wavefronts.
 int launch_pivot(void *stream, const PivotArgs &a, int k, int blocks);
 int max_pivot_blocks(int k);
+// Insert list[0, n) into the (cleared) hash set a.table.
+int launch_pivot_rehash(void *stream, const PivotArgs &a, uint32_t n);
 
 // ------------------------------------------------------------ kernels (kernels.hip)
 // enumeration kernel variants

@@ -55,4 +55,19 @@ int launch_pivot(void *stream, const PivotArgs &a, int k, int blocks) {
   return hipGetLastError() == hipSuccess ? BDEG_OK : BDEG_E_DEVICE;
 }
 
+namespace dev {
+// Rebuild the hash set from the work list after the set has grown: one
+// thread per listed cell (the list holds no duplicates).
+__global__ void __launch_bounds__(256) pivot_rehash_kernel(PivotArgs a, uint32_t n) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i < n) (void)set_insert(a, a.list[i]);
+}
+} // namespace dev
+
+int launch_pivot_rehash(void *stream, const PivotArgs &a, uint32_t n) {
+  if (n == 0) return BDEG_OK;
+  hipLaunchKernelGGL(dev::pivot_rehash_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, a, n);
+  return hipGetLastError() == hipSuccess ? BDEG_OK : BDEG_E_DEVICE;
+}
+
 } // namespace bdeg

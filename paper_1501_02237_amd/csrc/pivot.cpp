@@ -52,7 +52,44 @@ struct WalkResult {
   bool tie = false;
 };
 
-// One walk from `start`; BDEG_E_NOMEM when the device cannot hold the cells.
+// Make room for `need` cells: a larger work list (the listed cells copied)
+// and a hash set of twice that many slots rebuilt from the list, so the set's
+// load stays at most 1/2.
+int grow(Device *D, WalkBuffers &b, PivotArgs &a, uint64_t need, uint32_t tail) {
+  uint64_t cap = b.cap ? b.cap : (1ull << 20);
+  while (cap < need) cap *= 2;
+  if (cap > (1ull << 31)) return BDEG_E_NOMEM; // work-list indices are 32-bit
+  if (cap == b.cap) return BDEG_OK;
+  uint64_t *list = nullptr, *table = nullptr;
+  if (hipMalloc((void **)&list, cap * sizeof(uint64_t)) != hipSuccess) return BDEG_E_NOMEM;
+  if (hipMalloc((void **)&table, 2 * cap * sizeof(uint64_t)) != hipSuccess) {
+    (void)hipFree(list);
+    return BDEG_E_NOMEM;
+  }
+  if (hipMemsetAsync(table, 0, 2 * cap * sizeof(uint64_t), D->stream) != hipSuccess ||
+      (tail && hipMemcpyAsync(list, b.list, tail * sizeof(uint64_t), hipMemcpyDeviceToDevice, D->stream) !=
+                   hipSuccess) ||
+      hipStreamSynchronize(D->stream) != hipSuccess) {
+    (void)hipFree(list);
+    (void)hipFree(table);
+    return BDEG_E_DEVICE;
+  }
+  if (b.list) (void)hipFree(b.list);
+  if (b.table) (void)hipFree(b.table);
+  b.list = list;
+  b.table = table;
+  b.cap = cap;
+  a.list = list;
+  a.cap_list = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull);
+  a.table = table;
+  a.table_mask = 2 * cap - 1;
+  return launch_pivot_rehash(D->stream, a, tail);
+}
+
+// One walk from `start`, breadth first.  Before each level the list and the
+// set are grown to the level's worst case (every processed cell adds at most
+// k + 1 new ones), so a level never runs out of room; a probe sequence that
+// runs out anyway (PIVOT_ERR_FULL) restarts the walk with twice the room.
 int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k, uint64_t start,
          std::vector<uint64_t> *cells_out, WalkResult &out) {
   WalkBuffers b;
@@ -65,43 +102,36 @@ int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k,
     return BDEG_E_DEVICE;
   const int blocks = max_pivot_blocks(k);
   if (blocks <= 0) return BDEG_E_DEVICE;
-  for (uint64_t cap = 1ull << 20;; cap *= 2) {
-    if (cap > (1ull << 31)) return BDEG_E_NOMEM; // work-list indices are 32-bit
-    if (b.list) (void)hipFree(b.list);
-    if (b.table) (void)hipFree(b.table);
-    b.list = b.table = nullptr;
-    if (hipMalloc((void **)&b.list, cap * sizeof(uint64_t)) != hipSuccess ||
-        hipMalloc((void **)&b.table, 2 * cap * sizeof(uint64_t)) != hipSuccess)
-      return BDEG_E_NOMEM;
-    b.cap = cap;
-    const uint64_t tmask = 2 * cap - 1;
-    PivotCounters c0{};
-    c0.tail = 1;
-    if (hipMemsetAsync(b.table, 0, 2 * cap * sizeof(uint64_t), D->stream) != hipSuccess ||
-        hipMemcpyAsync(b.list, &start, sizeof start, hipMemcpyHostToDevice, D->stream) != hipSuccess ||
-        hipMemcpyAsync(b.table + (host_cell_hash(start) & tmask), &start, sizeof start, hipMemcpyHostToDevice,
-                       D->stream) != hipSuccess ||
-        hipMemcpyAsync(b.cnt, &c0, sizeof c0, hipMemcpyHostToDevice, D->stream) != hipSuccess)
-      return BDEG_E_DEVICE;
+  for (uint64_t room = 1ull << 20;; room *= 2) {
+    if (room > (1ull << 31)) return BDEG_E_NOMEM;
     PivotArgs a;
     a.pts = b.pts;
     a.hts = b.hts;
     a.N = N;
-    a.list = b.list;
-    a.cap_list = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull);
-    a.table = b.table;
-    a.table_mask = tmask;
     a.cnt = b.cnt;
+    // a fresh, empty list and set of `room` cells holding the start cell
+    b.cap = 0;
+    int rc = grow(D, b, a, room, 0);
+    if (rc) return rc;
+    PivotCounters c0{};
+    c0.tail = 1;
+    if (hipMemcpyAsync(b.list, &start, sizeof start, hipMemcpyHostToDevice, D->stream) != hipSuccess ||
+        hipMemcpyAsync(b.table + (host_cell_hash(start) & a.table_mask), &start, sizeof start,
+                       hipMemcpyHostToDevice, D->stream) != hipSuccess ||
+        hipMemcpyAsync(b.cnt, &c0, sizeof c0, hipMemcpyHostToDevice, D->stream) != hipSuccess)
+      return BDEG_E_DEVICE;
     uint32_t first = 0, count = 1;
     PivotCounters c{};
     bool regrow = false;
     while (count > 0) {
+      rc = grow(D, b, a, (uint64_t)first + count + (uint64_t)count * (k + 1), first + count);
+      if (rc) return rc;
       a.first = first;
       a.count = count;
       const uint32_t zero = 0;
       if (hipMemcpyAsync(&b.cnt->next, &zero, sizeof zero, hipMemcpyHostToDevice, D->stream) != hipSuccess)
         return BDEG_E_DEVICE;
-      int rc = launch_pivot(D->stream, a, k, blocks);
+      rc = launch_pivot(D->stream, a, k, blocks);
       if (rc) return rc;
       if (hipMemcpyAsync(&c, b.cnt, sizeof c, hipMemcpyDeviceToHost, D->stream) != hipSuccess ||
           hipStreamSynchronize(D->stream) != hipSuccess)
@@ -118,7 +148,10 @@ int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k,
       first += count;
       count = c.tail - first;
     }
-    if (regrow) continue;
+    if (regrow) {
+      room = std::max(room, b.cap);
+      continue;
+    }
     out.tie = false;
     out.nvol = ((u128)c.vol_hi << 64) | c.vol_lo;
     out.cells = c.cells;
