@@ -37,8 +37,8 @@ PEAK_ALU = 256 * 4 * 16 * 2.4e9  # 32-bit integer VALU lane-ops/s: CUs x SIMDs x
 # source the counters were taken on; any change to it makes `traffic` null.
 TRAFFIC = {
     "sources": ("enum_device.hpp", "exact_div.hpp", "kernels_k8.hip"),
-    "sha256": "4a029360e9152ccdcb38d7394f0540e2a5ef5124720511e3d55d135e575e6107",
-    "fetch_kib": 4388.98, "fetch_scale": 262144.0 / 131089.0,
+    "sha256": "89055dff530742876f0d991de2a9fc10d410e623985bd9f5645bfbd9187be976",
+    "fetch_kib": 4503.61, "fetch_scale": 262144.0 / 131089.0,
     "write_kib": 1966.16, "write_scale": 262144.0 / 262144.0,
 }
 
