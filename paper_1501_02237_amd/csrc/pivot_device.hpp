@@ -66,52 +66,70 @@ __device__ __forceinline__ bool set_insert(const PivotArgs &a, uint64_t m) {
   return false;
 }
 
-// Exact argmin over the lanes of num / den (den > 0; den == 0 marks a lane
-// without a candidate).  Returns the winning lane or -1; *tie is set when
-// another lane has the same minimal ratio (the flag travels with the current
-// minimum, so equal ratios above the minimum do not count).
+// Wave-wide minimum of an unsigned key (every lane active): a row-wise
+// shift scan with DPP, then the row broadcasts; lane 63 ends with the minimum.
+__device__ __forceinline__ uint32_t wave_umin(uint32_t v) {
+  constexpr int UMAX = -1; // identity of the minimum for lanes without a source
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(UMAX, (int)v, 0x111, 0xf, 0xf, false)); // row_shr:1
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(UMAX, (int)v, 0x112, 0xf, 0xf, false)); // row_shr:2
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(UMAX, (int)v, 0x114, 0xf, 0xf, false)); // row_shr:4
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(UMAX, (int)v, 0x118, 0xf, 0xf, false)); // row_shr:8
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(UMAX, (int)v, 0x142, 0xa, 0xf, false)); // row_bcast:15
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(UMAX, (int)v, 0x143, 0xc, 0xf, false)); // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Exact argmin over the lanes of num / den, for num >= 0 and den > 0 (den == 0
+// marks a lane without a candidate).  Returns the winning lane or -1; *tie is
+// set when another lane has the same minimal ratio.
+//   The ratios are screened in float: the key is the bit pattern of the
+// rounded ratio, monotone in it for ratios >= 0, with a relative error below
+// 2^-21 (two conversions, the reciprocal and the product, each within one
+// ulp).  Every lane whose exact ratio is the minimum has a key within 64 ulps
+// (a factor of at least 1 + 2^-17) of the smallest key, so only the lanes in
+// that band can win; when there are several they are compared exactly, with
+// 128-bit products, one by one.
 __device__ __forceinline__ int ratio_argmin(int64_t num, int32_t den, bool *tie) {
-  int idx = den > 0 ? (int)(threadIdx.x & 63) : -1;
+  constexpr uint32_t BAND = 64;
+  const bool has = den > 0;
+  const float fn = __builtin_fmaf((float)(int32_t)(num >> 32), 4294967296.0f, (float)(uint32_t)num);
+  const float r = fn * __builtin_amdgcn_rcpf((float)den);
+  const uint32_t key = has ? __float_as_uint(r) : 0xFFFFFFFFu;
+  const uint32_t kmin = wave_umin(key);
+  *tie = false;
+  if (kmin == 0xFFFFFFFFu) return -1;
+  uint64_t near = pballot(has && key - kmin <= BAND);
+  int best = __builtin_ctzll(near);
+  near &= near - 1;
+  if (!near) return best;
+  // several lanes in the band: exact comparison, the tie travels with the minimum
+  const int32_t nlo = (int32_t)(uint32_t)num, nhi = (int32_t)((uint64_t)num >> 32);
+  int64_t bn = (int64_t)(((uint64_t)(uint32_t)prl(nhi, best) << 32) | (uint32_t)prl(nlo, best));
+  int32_t bd = prl(den, best);
   bool t = false;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const int src = (int)(threadIdx.x & 63) ^ d;
-    const int32_t olo = pbp((int32_t)(uint32_t)num, src);
-    const int32_t ohi = pbp((int32_t)(uint32_t)((uint64_t)num >> 32), src);
-    const int32_t oden = pbp(den, src);
-    const int oidx = pbp(idx, src);
-    const bool ot = pbp((int32_t)t, src) != 0;
-    const int64_t onum = (int64_t)(((uint64_t)(uint32_t)ohi << 32) | (uint32_t)olo);
-    // (a partner half without a candidate changes nothing)
-    if (oidx >= 0 && idx < 0) {
-      num = onum;
-      den = oden;
-      idx = oidx;
-      t = ot;
-    } else if (oidx >= 0) {
-      const __int128 lhs = (__int128)onum * den, rhs = (__int128)num * oden;
-      if (lhs < rhs) { // the partner's minimum is smaller
-        num = onum;
-        den = oden;
-        idx = oidx;
-        t = ot;
-      } else if (lhs == rhs) { // the same ratio in both halves
-        if (oidx < idx) {
-          num = onum;
-          den = oden;
-          idx = oidx;
-        }
-        t = true;
-      }
+  while (near) {
+    const int j = __builtin_ctzll(near);
+    near &= near - 1;
+    const int64_t jn = (int64_t)(((uint64_t)(uint32_t)prl(nhi, j) << 32) | (uint32_t)prl(nlo, j));
+    const int32_t jd = prl(den, j);
+    const __int128 lhs = (__int128)jn * bd, rhs = (__int128)bn * jd;
+    if (lhs < rhs) {
+      best = j;
+      bn = jn;
+      bd = jd;
+      t = false;
+    } else if (lhs == rhs) {
+      t = true;
     }
   }
   *tie = t;
-  return __builtin_amdgcn_readfirstlane(idx);
+  return best;
 }
 
 template <int K>
 __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
   const int lane = (int)(threadIdx.x & 63);
+  uint64_t vol = 0, cells = 0; // this wave's cells (uniform across the wave)
   for (;;) {
     // Every lane takes part in the claim (lane 0 adds one, the others zero)
     // and lane 0's result is read by index.  A claim made under a lane-0 branch
@@ -182,18 +200,16 @@ __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
       continue;
     }
     if (on && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE);
-    if (lane == 0) {
-      const unsigned long long vd = (unsigned long long)(neg ? -(int64_t)D : (int64_t)D);
-      const unsigned long long old = atomicAdd(&a.cnt->vol_lo, vd);
-      if (old + vd < old) atomicAdd(&a.cnt->vol_hi, 1ull);
-      atomicAdd(&a.cnt->cells, 1ull);
-    }
+    vol += (uint64_t)(neg ? -(int64_t)D : (int64_t)D);
+    cells++;
     // barycentric coordinate of the base point, times D
     int64_t sum = 0;
 #pragma unroll
     for (int t = 0; t < K; t++) sum += x[t];
     const int64_t c0 = (int64_t)D - sum;
-    // facets: opposite the point pivoted at step t (row t), then opposite v0
+    // facets: opposite the point pivoted at step t (row t), then opposite v0;
+    // lane t keeps the neighbour across facet t
+    uint64_t mine = 0;
 #pragma unroll
     for (int t = 0; t <= K; t++) {
       const int64_t c = t < K ? (int64_t)x[t] : c0;
@@ -204,16 +220,23 @@ __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
       if (tie && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE);
       if (u >= 0) { // (none: the facet is on the boundary of the hull)
         const int v = t < K ? pivlane[t] : v0;
-        const uint64_t nb = (C & ~(1ull << v)) | (1ull << u);
-        if (lane == 0 && set_insert(a, nb)) {
-          const uint32_t pos = atomicAdd(&a.cnt->tail, 1u);
-          if (pos < a.cap_list)
-            a.list[pos] = nb;
-          else
-            atomicOr(&a.cnt->flags, PIVOT_ERR_FULL);
-        }
+        if (lane == t) mine = (C & ~(1ull << v)) | (1ull << u);
       }
     }
+    // lane t inserts the neighbour across facet t: all probes in one round
+    if (mine && set_insert(a, mine)) {
+      const uint32_t pos = atomicAdd(&a.cnt->tail, 1u);
+      if (pos < a.cap_list)
+        a.list[pos] = mine;
+      else
+        atomicOr(&a.cnt->flags, PIVOT_ERR_FULL);
+    }
+  }
+  // the wave's tallies (uniform values) in one update
+  if (lane == 0 && cells) {
+    const unsigned long long old = atomicAdd(&a.cnt->vol_lo, (unsigned long long)vol);
+    if (old + vol < old) atomicAdd(&a.cnt->vol_hi, 1ull);
+    atomicAdd(&a.cnt->cells, (unsigned long long)cells);
   }
 }
 

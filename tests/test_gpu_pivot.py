@@ -71,7 +71,9 @@ def _points(seed, N, k, lo=-2, hi=2):
 
 
 @pytest.mark.parametrize("N,k,bits", [(5, 1, 12), (8, 2, 16), (12, 3, 16), (16, 4, 20), (20, 5, 20), (24, 6, 20),
-                                       (33, 4, 20), (40, 3, 20), (18, 8, 16), (16, 10, 16), (64, 2, 24)])
+                                       (33, 4, 20), (40, 3, 20), (18, 8, 16), (16, 10, 16), (64, 2, 24),
+                                       # heights of 1-2 bits: non-generic liftings, the tie must be reported
+                                       (12, 2, 1), (10, 3, 1), (16, 3, 2), (9, 2, 2)])
 def test_walk_matches_oracle_cells(N, k, bits):
     P = _points(0x9A1 + N, N, k)
     start, H = _lifting(P, 0x9A2 + N * 7 + k, bits)
