@@ -67,6 +67,33 @@ def ops_per_launch(stats: dict, N: int, k: int) -> float:
     return N * (8.0 * sp + 24.0 * ht) + 20.0 * (N - k - 1) * stats["leaves"]
 
 
+def walk_ops_per_cell(N: int, k: int) -> float:
+    """Algorithmic 32-bit integer operations of one cell of the walk (same op
+    model as the enumeration): k fraction-free Gauss-Jordan steps over N lane
+    columns, each updating k - 1 spatial entries (8) and the height entry (24),
+    then k + 1 ratio screens of 12 per lane (conversions, reciprocal, product,
+    band test and the share of the wave minimum)."""
+    return N * (k * (8 * (k - 1) + 24) + 12 * (k + 1))
+
+
+def walk_leg(bd, gen, m: int, k: int) -> dict:
+    """The cell walk on the Table 4 system W_{m,k}, end to end (prologue,
+    allocation, every level) after a warm-up walk, checked against the
+    paper's degree."""
+    with open(os.path.join(ROOT, "tests", "golden", "paper_values.json")) as fh:
+        deg = json.load(fh)["table4_degrees"][f"{m},{k}"]
+    A = gen.master_space_matrix(m, k)
+    bd.degree_pivot(gen.master_space_matrix(3, 4), seed=5, lift_bits=20)
+    t = time.perf_counter()
+    r = bd.degree_pivot(A, seed=5, lift_bits=20)
+    wt = time.perf_counter() - t
+    assert r["status"] == 0 and r["comps"] * r["nvol"] == deg, (r, deg)
+    N = len(A[0]) + 1
+    log(f"[bench] walk W_{m},{k}: k={r['k']} N={N} {r['cells']} cells in {wt:.3f} s")
+    return {"s": round(wt, 4), "cells": r["cells"], "cells_per_s": r["cells"] / wt,
+            "alu_frac": r["cells"] * walk_ops_per_cell(N, r["k"]) / wt / PEAK_ALU}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -139,6 +166,8 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a dispatch of known "
                          "traffic, for scaling hardware byte counters)")
+    ap.add_argument("--walk", default="",
+                    help="M,K: run only the cell walk on the Table 4 system W_{M,K} and print its figures")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {a.gpus}); "
@@ -160,6 +189,11 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {a.calibrate_copy_mib} MiB read + {a.calibrate_copy_mib} MiB written")
         del src, dst
+
+    if a.walk:
+        m, k = (int(x) for x in a.walk.split(","))
+        print(json.dumps({"walk": f"W_{{{m},{k}}}", **walk_leg(bd, gen, m, k)}), flush=True)
+        return
 
     s2 = gen.cfg2_system()
     N2, k2 = s2.n + 1, s2.n - s2.m
@@ -253,6 +287,9 @@ def main():
         extra["large36_kernel_ms"] = round(st4["kernel_ms"], 3)
         extra["large36_cand_per_s"] = cand4 / (st4["total_ms"] * 1e-3)
         log(f"[bench] n=36 k=10: nvol={r4['nvol']} kernel {st4['kernel_ms']:.2f} ms")
+
+        # the cell walk on the largest Table 4 system, W_{4,5} (k = 22, N = 61)
+        extra.update({f"walk_w45_{key}": v for key, v in walk_leg(bd, gen, 4, 5).items()})
 
         if a.serve_requests > 0:
             extra.update(serve_trace(bd, gen, a.serve_requests))
