@@ -32,6 +32,7 @@
 
 #include "bdeg_internal.hpp"
 #include "exact_div.hpp"
+#include "wave_ratio.hpp"
 
 namespace bdeg {
 namespace dev {
@@ -64,66 +65,6 @@ __device__ __forceinline__ bool set_insert(const PivotArgs &a, uint64_t m) {
   }
   atomicOr(&a.cnt->flags, PIVOT_ERR_FULL);
   return false;
-}
-
-// Wave-wide minimum of an unsigned key (every lane active): a row-wise
-// shift scan with DPP, then the row broadcasts; lane 63 ends with the minimum.
-__device__ __forceinline__ uint32_t wave_umin(uint32_t v) {
-  constexpr int UMAX = -1; // identity of the minimum for lanes without a source
-  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(UMAX, (int)v, 0x111, 0xf, 0xf, false)); // row_shr:1
-  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(UMAX, (int)v, 0x112, 0xf, 0xf, false)); // row_shr:2
-  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(UMAX, (int)v, 0x114, 0xf, 0xf, false)); // row_shr:4
-  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(UMAX, (int)v, 0x118, 0xf, 0xf, false)); // row_shr:8
-  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(UMAX, (int)v, 0x142, 0xa, 0xf, false)); // row_bcast:15
-  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(UMAX, (int)v, 0x143, 0xc, 0xf, false)); // row_bcast:31
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
-}
-
-// Exact argmin over the lanes of num / den, for num >= 0 and den > 0 (den == 0
-// marks a lane without a candidate).  Returns the winning lane or -1; *tie is
-// set when another lane has the same minimal ratio.
-//   The ratios are screened in float: the key is the bit pattern of the
-// rounded ratio, monotone in it for ratios >= 0, with a relative error below
-// 2^-21 (two conversions, the reciprocal and the product, each within one
-// ulp).  Every lane whose exact ratio is the minimum has a key within 64 ulps
-// (a factor of at least 1 + 2^-17) of the smallest key, so only the lanes in
-// that band can win; when there are several they are compared exactly, with
-// 128-bit products, one by one.
-__device__ __forceinline__ int ratio_argmin(int64_t num, int32_t den, bool *tie) {
-  constexpr uint32_t BAND = 64;
-  const bool has = den > 0;
-  const float fn = __builtin_fmaf((float)(int32_t)(num >> 32), 4294967296.0f, (float)(uint32_t)num);
-  const float r = fn * __builtin_amdgcn_rcpf((float)den);
-  const uint32_t key = has ? __float_as_uint(r) : 0xFFFFFFFFu;
-  const uint32_t kmin = wave_umin(key);
-  *tie = false;
-  if (kmin == 0xFFFFFFFFu) return -1;
-  uint64_t near = pballot(has && key - kmin <= BAND);
-  int best = __builtin_ctzll(near);
-  near &= near - 1;
-  if (!near) return best;
-  // several lanes in the band: exact comparison, the tie travels with the minimum
-  const int32_t nlo = (int32_t)(uint32_t)num, nhi = (int32_t)((uint64_t)num >> 32);
-  int64_t bn = (int64_t)(((uint64_t)(uint32_t)prl(nhi, best) << 32) | (uint32_t)prl(nlo, best));
-  int32_t bd = prl(den, best);
-  bool t = false;
-  while (near) {
-    const int j = __builtin_ctzll(near);
-    near &= near - 1;
-    const int64_t jn = (int64_t)(((uint64_t)(uint32_t)prl(nhi, j) << 32) | (uint32_t)prl(nlo, j));
-    const int32_t jd = prl(den, j);
-    const __int128 lhs = (__int128)jn * bd, rhs = (__int128)bn * jd;
-    if (lhs < rhs) {
-      best = j;
-      bn = jn;
-      bd = jd;
-      t = false;
-    } else if (lhs == rhs) {
-      t = true;
-    }
-  }
-  *tie = t;
-  return best;
 }
 
 template <int K>
@@ -191,7 +132,7 @@ __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
     const int32_t D = prev;
     const bool neg = D < 0;
     // height above the cell's hyperplane, times |D|
-    const int64_t s_raw = ((int64_t)H1 << 31) + (int64_t)(uint32_t)H0;
+    const int64_t s_raw = (int64_t)H1 * ((int64_t)1 << 31) + (int64_t)(uint32_t)H0;
     const int64_t S = neg ? -s_raw : s_raw;
     const bool other = valid && !in_cell;
     const uint64_t below = pballot(other && S < 0), on = pballot(other && S == 0);
@@ -215,9 +156,9 @@ __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
       const int64_t c = t < K ? (int64_t)x[t] : c0;
       const int64_t cs = neg ? -c : c; // lambda * |D|
       const bool beyond = other && cs < 0;
-      bool tie = false;
-      const int u = ratio_argmin(beyond ? S : 0, beyond ? (int32_t)(-cs) : 0, &tie);
-      if (tie && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE);
+      const RatioMin rm = ratio_min(beyond ? S : 0, beyond ? (int32_t)(-cs) : 0);
+      const int u = rm.lane;
+      if ((rm.lanes & (rm.lanes - 1)) && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE); // equal minima
       if (u >= 0) { // (none: the facet is on the boundary of the hull)
         const int v = t < K ? pivlane[t] : v0;
         if (lane == t) mine = (C & ~(1ull << v)) | (1ull << u);
