@@ -195,6 +195,36 @@ int bdeg_subdivision(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int3
                      int64_t *normal_num, uint64_t *normal_den, uint64_t *n_cells, bdeg_result *out);
 
 /*
+ * bdeg_nvol_points over all candidates, with prefix pruning (Section 4.1: a
+ * set of points that is not a lower face extends to no lower facet).  The
+ * candidates are split by their top d = k + 1 - W points; one wavefront per
+ * such prefix decides, with a float simplex whose answer is then certified in
+ * exact integer arithmetic, whether the prefix lies in a lower face, and only
+ * the subtrees of prefixes that may are enumerated.  The results are those of
+ * bdeg_nvol_points (a pruned subtree holds no lower facet and no tie).
+ *   width      W, 1..8 free columns of the tested prefix states (0: 5, widened
+ *              while the prefixes would exceed BDEG_PRUNE_MAX_PREFIXES);
+ *              BDEG_E_TOO_LARGE when they still would;
+ *   *nvol, *tie, *cells   as for bdeg_nvol_points;
+ *   stats      optional (NULL): prefixes, degenerate and pruned ones, units
+ *              enumerated, simplex pivots, device times of both phases.
+ */
+#define BDEG_PRUNE_MAX_PREFIXES (1ull << 24)
+typedef struct bdeg_prune_stats {
+  uint64_t prefixes;   /* prefixes tested */
+  uint64_t degenerate; /* prefixes whose points are affinely dependent (no candidate below) */
+  uint64_t pruned;     /* prefixes certified to lie in no lower face */
+  uint64_t units;      /* work units enumerated below the other prefixes */
+  uint64_t pivots;     /* simplex pivots of all tests */
+  int32_t prefix_size; /* d */
+  int32_t width;       /* W = k + 1 - d */
+  float filter_ms;     /* device time of the prefix tests */
+  float enum_ms;       /* device time of the enumeration of the units kept */
+} bdeg_prune_stats;
+int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, int32_t width,
+                            bdeg_u128 *nvol, int32_t *tie, uint64_t *cells, bdeg_prune_stats *stats);
+
+/*
  * The regular subdivision by simplicial pivoting (Section 4.2-4.4): instead
  * of deciding every (k+1)-subset, walk from one cell to its neighbours across
  * facets (for the facet opposite v, the new vertex minimizes the height above

@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
         "bdeg_batch_profile": ([P], ctypes.c_int),
         "bdeg_batch_destroy": ([P], ctypes.c_int),
         "bdeg_nvol_points": ([P, P, I32, I32, U64, U64, P, P, P], ctypes.c_int),
+        "bdeg_nvol_points_pruned": ([P, P, I32, I32, I32, P, P, P, P], ctypes.c_int),
         "bdeg_kernel_points": ([P, I32, I32, P, P, P, P], ctypes.c_int),
         "bdeg_consistency": ([P, I32, I32, P, ctypes.c_double, P, P, P], ctypes.c_int),
         "bdeg_pivot_points": ([P, P, I32, I32, U64, U64, P, P, P, P], ctypes.c_int),
@@ -181,6 +182,30 @@ def pivot_points(points, heights, start_mask: int, cap: int = 0) -> dict:
     if rc != BDEG_OK:
         raise BdegError(rc, "bdeg_pivot_points")
     return dict(nvol=nv.value, cells=n.value, tie=bool(tie.value), masks=masks[: min(cap, n.value)].copy())
+
+
+class PruneStats(ctypes.Structure):
+    _fields_ = [
+        ("prefixes", ctypes.c_uint64), ("degenerate", ctypes.c_uint64), ("pruned", ctypes.c_uint64),
+        ("units", ctypes.c_uint64), ("pivots", ctypes.c_uint64), ("prefix_size", ctypes.c_int32),
+        ("width", ctypes.c_int32), ("filter_ms", ctypes.c_float), ("enum_ms", ctypes.c_float),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def nvol_points_pruned(points, heights, width: int = 0) -> dict:
+    """bdeg_nvol_points over all candidates with prefix pruning: {nvol, tie, cells, stats}."""
+    P = np.ascontiguousarray(np.asarray(points, dtype=np.int32))
+    H = np.ascontiguousarray(np.asarray(heights, dtype=np.int64))
+    N, k = P.shape
+    nv, tie, cells, ps = U128(), ctypes.c_int32(), ctypes.c_uint64(), PruneStats()
+    rc = lib().bdeg_nvol_points_pruned(P.ctypes.data, H.ctypes.data, N, k, width, ctypes.byref(nv),
+                                       ctypes.byref(tie), ctypes.byref(cells), ctypes.byref(ps))
+    if rc != BDEG_OK:
+        raise BdegError(rc, "bdeg_nvol_points_pruned")
+    return dict(nvol=nv.value, tie=bool(tie.value), cells=cells.value, stats=ps.as_dict())
 
 
 def degree_batch(mats, seed: int = 1, lift_bits: int = 20) -> list[dict]:

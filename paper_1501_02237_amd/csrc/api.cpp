@@ -551,6 +551,120 @@ int bdeg_nvol_points(const int32_t *points, const int64_t *heights, int32_t N, i
   return BDEG_OK;
 }
 
+int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, int32_t width,
+                            bdeg_u128 *nvol, int32_t *tie, uint64_t *cells, bdeg_prune_stats *ps) {
+  if (!nvol || !tie) return BDEG_E_ARG;
+  int rc = check_points(points, heights, N, k);
+  if (rc) return rc;
+  // prefix states with W free columns: W = width (0: 5, widened while the
+  // prefixes would be too many)
+  int W = width > 0 ? width : std::min(k, 5);
+  if (W < 1 || W > PRUNE_WMAX || W > k) return BDEG_E_ARG;
+  if (width <= 0)
+    while (W < PRUNE_WMAX && W < k && binom_u64(N - W, k + 1 - W) > BDEG_PRUNE_MAX_PREFIXES) W++;
+  const int d = k + 1 - W; // prefix size; its lowest element is >= W
+  const uint64_t n_items = binom_u64(N - W, d);
+  if (n_items > BDEG_PRUNE_MAX_PREFIXES) return BDEG_E_TOO_LARGE;
+  // the prefixes: d-subsets of {W, .., N-1}; each kept one gives e - W + 1 units
+  std::vector<uint64_t> items;
+  items.reserve((size_t)n_items);
+  uint64_t cap_units = 0;
+  // d-subsets of {0, .., N-W-1} in increasing order (Gosper), shifted up by W
+  const uint64_t lim = (1ull << (N - W)) - 1; // N - W < 64
+  for (uint64_t m = (1ull << d) - 1; m <= lim;) {
+    items.push_back(m << W);
+    cap_units += (uint64_t)__builtin_ctzll(m) + 1; // next elements W-1 .. e-1 of the lowest e
+    const uint64_t c = m & (0 - m), r = m + c;
+    m = (((r ^ m) >> 2) / c) | r;
+  }
+  if (cap_units == 0 || cap_units > 0xFFFFFFFFull) return BDEG_E_TOO_LARGE;
+  int st;
+  Device *D = device_get(&st);
+  if (!D) return st;
+  std::lock_guard<std::mutex> lk(D->mu);
+  Job job;
+  points_job(job, points, heights, N, k, 0, 0); // no units: they come from the prefixes
+  if ((rc = job_upload(job)) || (rc = job_launch_pre(job, D->stream))) return rc;
+  uint64_t *d_items = nullptr;
+  Tile *d_units = nullptr;
+  PruneCounters *d_pc = nullptr;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  auto cleanup = [&]() {
+    if (d_items) (void)hipFree(d_items);
+    if (d_units) (void)hipFree(d_units);
+    if (d_pc) (void)hipFree(d_pc);
+    for (hipEvent_t &e : ev)
+      if (e) (void)hipEventDestroy(e);
+  };
+  if (hipMalloc((void **)&d_items, items.size() * sizeof(uint64_t)) != hipSuccess ||
+      hipMalloc((void **)&d_units, cap_units * sizeof(Tile)) != hipSuccess ||
+      hipMalloc((void **)&d_pc, sizeof(PruneCounters)) != hipSuccess) {
+    cleanup();
+    return BDEG_E_NOMEM;
+  }
+  PruneCounters pc{};
+  for (hipEvent_t &e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      cleanup();
+      return BDEG_E_DEVICE;
+    }
+  if (hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(uint64_t), hipMemcpyHostToDevice, D->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(d_pc, &pc, sizeof pc, hipMemcpyHostToDevice, D->stream) != hipSuccess ||
+      hipEventRecord(ev[0], D->stream) != hipSuccess) {
+    cleanup();
+    return BDEG_E_DEVICE;
+  }
+  PruneArgs a;
+  a.pts = job.d_pts;
+  a.hts = job.d_hts;
+  a.N = N;
+  a.K = k;
+  a.W = W;
+  a.items = d_items;
+  a.n_items = (uint32_t)items.size();
+  a.units = d_units;
+  a.cap_units = (uint32_t)cap_units;
+  a.cnt = d_pc;
+  rc = launch_prune(D->stream, a);
+  if (!rc && (hipEventRecord(ev[1], D->stream) != hipSuccess ||
+              hipMemcpyAsync(&pc, d_pc, sizeof pc, hipMemcpyDeviceToHost, D->stream) != hipSuccess ||
+              hipStreamSynchronize(D->stream) != hipSuccess))
+    rc = BDEG_E_DEVICE;
+  if (!rc && pc.overflow) rc = BDEG_E_STATE; // cannot happen: the buffer holds every unit
+  if (!rc) {
+    LaunchShape shape = job.shape;
+    shape.single = single_group(N);
+    shape.mode = MODE_PLAIN;
+    rc = launch_enumerate(D->stream, job.d_sys, job.d_pts, job.d_hts, d_units, pc.units, job.d_acc, job.d_cnt, k, k,
+                          shape);
+  }
+  if (!rc && hipEventRecord(ev[2], D->stream) != hipSuccess) rc = BDEG_E_DEVICE;
+  std::vector<SysAcc> acc;
+  if (!rc) rc = job_collect(job, D->stream, acc, nullptr);
+  if (!rc) {
+    *nvol = bdeg_u128{acc[0].lo, acc[0].hi};
+    *tie = (int32_t)acc[0].tie;
+    if (cells) *cells = acc[0].cells;
+    if (ps) {
+      float f = 0.f, g = 0.f;
+      (void)hipEventElapsedTime(&f, ev[0], ev[1]);
+      (void)hipEventElapsedTime(&g, ev[1], ev[2]);
+      ps->prefixes = items.size();
+      ps->degenerate = pc.degenerate;
+      ps->pruned = pc.pruned;
+      ps->units = pc.units;
+      ps->pivots = pc.pivots;
+      ps->prefix_size = d;
+      ps->width = W;
+      ps->filter_ms = f;
+      ps->enum_ms = g;
+    }
+  }
+  cleanup();
+  return rc;
+}
+
 int bdeg_cells_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, uint64_t rank_lo,
                       uint64_t rank_hi, uint64_t cap, uint64_t *cell_masks, int64_t *normal_num,
                       uint64_t *normal_den, uint64_t *n_cells, int32_t *tie) {

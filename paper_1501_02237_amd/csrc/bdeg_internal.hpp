@@ -132,6 +132,30 @@ int max_pivot_blocks(int k);
 // Insert list[0, n) into the (cleared) hash set a.table.
 int launch_pivot_rehash(void *stream, const PivotArgs &a, uint32_t n);
 
+// ------------------------------------------------------------ prefix pruning (kernels_prune.hip)
+constexpr int PRUNE_WMAX = 8; // widest prefix state tested (free spatial columns)
+struct PruneCounters {
+  uint32_t next;             // item head
+  uint32_t units;            // work units emitted
+  uint32_t degenerate;       // prefixes whose points are affinely dependent
+  uint32_t pruned;           // prefixes certified to lie in no lower face
+  unsigned long long pivots; // simplex pivots of all tests
+  uint32_t overflow;         // the unit buffer was too small
+  uint32_t pad;
+};
+struct PruneArgs {
+  const int32_t *pts; // N x K
+  const int64_t *hts; // N
+  int N, K, W;        // W = K + 1 - |prefix|
+  const uint64_t *items;
+  uint32_t n_items;   // prefixes (vertex masks), all with K + 1 - W points
+  Tile *units;        // out: one unit per next element below each prefix kept
+  uint32_t cap_units;
+  PruneCounters *cnt;
+};
+// One wavefront per prefix: eliminate it, test it, emit the units below it.
+int launch_prune(void *stream, const PruneArgs &a);
+
 // ------------------------------------------------------------ kernels (kernels.hip)
 // enumeration kernel variants
 constexpr int MODE_PLAIN = 0; // volume, cell count and tie flag

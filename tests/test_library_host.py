@@ -91,6 +91,21 @@ def test_argument_errors():
     assert e.value.code == bd.BDEG_E_ARG
 
 
+def test_pruned_argument_errors_before_any_device_work():
+    P = np.array([[0, 0], [1, 0], [0, 1], [1, 1]], dtype=np.int32)
+    H = np.array([0, 1, 2, 5], dtype=np.int64)
+    for width in (3, 9):  # wider than k, wider than the widest prefix state
+        with pytest.raises(bd.BdegError) as e:
+            bd.nvol_points_pruned(P, H, width=width)
+        assert e.value.code == bd.BDEG_E_ARG
+    # C(64 - 8, 11) prefixes exceed the limit even at the widest state
+    P = np.zeros((64, 18), dtype=np.int32)  # unit vectors: every minor is 0 or +-1
+    P[np.arange(64), np.arange(64) % 18] = 1
+    with pytest.raises(bd.BdegError) as e:
+        bd.nvol_points_pruned(P, np.arange(64, dtype=np.int64))
+    assert e.value.code == bd.BDEG_E_TOO_LARGE
+
+
 def test_host_overflow_is_reported():
     # kernel vector of [1, -2^40]: entries around 2^40 fit int64 but not the int32 point format
     A = np.array([[1, -(1 << 40)]], dtype=np.int64)
