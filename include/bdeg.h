@@ -203,8 +203,8 @@ int bdeg_subdivision(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int3
  * the subtrees of prefixes that may are enumerated.  The results are those of
  * bdeg_nvol_points (a pruned subtree holds no lower facet and no tie).
  *   width      W, 1..8 free columns of the tested prefix states (0: 5, widened
- *              while the prefixes would exceed BDEG_PRUNE_MAX_PREFIXES);
- *              BDEG_E_TOO_LARGE when they still would;
+ *              while there are more than 2^18 prefixes); BDEG_E_TOO_LARGE when
+ *              the prefixes exceed BDEG_PRUNE_MAX_PREFIXES;
  *   *nvol, *tie, *cells   as for bdeg_nvol_points;
  *   stats      optional (NULL): prefixes, degenerate and pruned ones, units
  *              enumerated, simplex pivots, device times of both phases.

@@ -556,26 +556,63 @@ int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32
   if (!nvol || !tie) return BDEG_E_ARG;
   int rc = check_points(points, heights, N, k);
   if (rc) return rc;
-  // prefix states with W free columns: W = width (0: 5, widened while the
-  // prefixes would be too many)
+  // prefix states with W free columns: W = width, or 5 widened while there
+  // are more than 2^18 prefixes (the tests then cost more than they save)
   int W = width > 0 ? width : std::min(k, 5);
   if (W < 1 || W > PRUNE_WMAX || W > k) return BDEG_E_ARG;
   if (width <= 0)
-    while (W < PRUNE_WMAX && W < k && binom_u64(N - W, k + 1 - W) > BDEG_PRUNE_MAX_PREFIXES) W++;
+    while (W < PRUNE_WMAX && W < k && binom_u64(N - W, k + 1 - W) > (1ull << 18)) W++;
   const int d = k + 1 - W; // prefix size; its lowest element is >= W
   const uint64_t n_items = binom_u64(N - W, d);
   if (n_items > BDEG_PRUNE_MAX_PREFIXES) return BDEG_E_TOO_LARGE;
   // the prefixes: d-subsets of {W, .., N-1}; each kept one gives e - W + 1 units
   std::vector<uint64_t> items;
   items.reserve((size_t)n_items);
-  uint64_t cap_units = 0;
-  // d-subsets of {0, .., N-W-1} in increasing order (Gosper), shifted up by W
+  // d-subsets of {0, .., N-W-1} in increasing order (Gosper), shifted up by W;
+  // a prefix with lowest point e gives one unit for each next element
+  // c = W-1 .. e-1, which goes to bucket c
+  uint64_t per_c[64] = {0};
   const uint64_t lim = (1ull << (N - W)) - 1; // N - W < 64
   for (uint64_t m = (1ull << d) - 1; m <= lim;) {
     items.push_back(m << W);
-    cap_units += (uint64_t)__builtin_ctzll(m) + 1; // next elements W-1 .. e-1 of the lowest e
+    per_c[__builtin_ctzll(m) + W]++; // prefixes with lowest point e = ctz + W
     const uint64_t c = m & (0 - m), r = m + c;
     m = (((r ^ m) >> 2) / c) | r;
+  }
+  // chunk c: the subtree of F + c split into runs of the following element
+  // (each run at most the plain plan's unit cost); one run [c, c] when F + c
+  // is already a whole candidate (W = 1)
+  const uint64_t max_cost = choose_max_cost(binom_u64(N, k + 1), default_waves(k, k, 4));
+  std::vector<uint16_t> chunk_start(65, 0);
+  std::vector<uint8_t> run_lo, run_hi;
+  for (int c = 0; c < 64; c++) {
+    chunk_start[c] = (uint16_t)run_lo.size();
+    if (c < W - 1 || c >= N) continue;
+    if (W == 1) {
+      run_lo.push_back((uint8_t)c);
+      run_hi.push_back((uint8_t)c);
+      continue;
+    }
+    // element after c: c2 in [W-2, c-1], C(c2, W-2) candidates each
+    int hi = c - 1;
+    while (hi >= W - 2) {
+      int lo = hi;
+      uint64_t cost = binom_u64(hi, W - 2);
+      while (lo - 1 >= W - 2 && cost + binom_u64(lo - 1, W - 2) <= max_cost) cost += binom_u64(--lo, W - 2);
+      run_lo.push_back((uint8_t)lo);
+      run_hi.push_back((uint8_t)hi);
+      hi = lo - 1;
+    }
+  }
+  chunk_start[64] = (uint16_t)run_lo.size();
+  if (run_lo.empty()) return BDEG_E_TOO_LARGE;
+  // bucket c holds chunk c of every prefix with e > c; laid out from c = N-1 down
+  uint32_t off[64] = {0};
+  uint64_t cap_units = 0, above = 0;
+  for (int c = N - 1; c >= W - 1; c--) {
+    off[c] = (uint32_t)std::min<uint64_t>(cap_units, 0xFFFFFFFFull);
+    cap_units += above * (uint64_t)(chunk_start[c + 1] - chunk_start[c]); // prefixes whose lowest point is above c
+    above += per_c[c];
   }
   if (cap_units == 0 || cap_units > 0xFFFFFFFFull) return BDEG_E_TOO_LARGE;
   int st;
@@ -586,19 +623,32 @@ int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32
   points_job(job, points, heights, N, k, 0, 0); // no units: they come from the prefixes
   if ((rc = job_upload(job)) || (rc = job_launch_pre(job, D->stream))) return rc;
   uint64_t *d_items = nullptr;
-  Tile *d_units = nullptr;
+  Tile *d_raw = nullptr, *d_units = nullptr;
   PruneCounters *d_pc = nullptr;
+  uint32_t *d_off = nullptr, *d_bcnt = nullptr;
+  uint16_t *d_cs = nullptr;
+  uint8_t *d_rlo = nullptr, *d_rhi = nullptr;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   auto cleanup = [&]() {
     if (d_items) (void)hipFree(d_items);
+    if (d_raw) (void)hipFree(d_raw);
     if (d_units) (void)hipFree(d_units);
     if (d_pc) (void)hipFree(d_pc);
+    if (d_off) (void)hipFree(d_off);
+    if (d_bcnt) (void)hipFree(d_bcnt);
+    if (d_cs) (void)hipFree(d_cs);
+    if (d_rlo) (void)hipFree(d_rlo);
+    if (d_rhi) (void)hipFree(d_rhi);
     for (hipEvent_t &e : ev)
       if (e) (void)hipEventDestroy(e);
   };
   if (hipMalloc((void **)&d_items, items.size() * sizeof(uint64_t)) != hipSuccess ||
+      hipMalloc((void **)&d_raw, cap_units * sizeof(Tile)) != hipSuccess ||
       hipMalloc((void **)&d_units, cap_units * sizeof(Tile)) != hipSuccess ||
-      hipMalloc((void **)&d_pc, sizeof(PruneCounters)) != hipSuccess) {
+      hipMalloc((void **)&d_pc, sizeof(PruneCounters)) != hipSuccess ||
+      hipMalloc((void **)&d_off, sizeof off) != hipSuccess || hipMalloc((void **)&d_bcnt, sizeof off) != hipSuccess ||
+      hipMalloc((void **)&d_cs, chunk_start.size() * sizeof(uint16_t)) != hipSuccess ||
+      hipMalloc((void **)&d_rlo, run_lo.size()) != hipSuccess || hipMalloc((void **)&d_rhi, run_hi.size()) != hipSuccess) {
     cleanup();
     return BDEG_E_NOMEM;
   }
@@ -611,6 +661,12 @@ int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32
   if (hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(uint64_t), hipMemcpyHostToDevice, D->stream) !=
           hipSuccess ||
       hipMemcpyAsync(d_pc, &pc, sizeof pc, hipMemcpyHostToDevice, D->stream) != hipSuccess ||
+      hipMemcpyAsync(d_off, off, sizeof off, hipMemcpyHostToDevice, D->stream) != hipSuccess ||
+      hipMemsetAsync(d_bcnt, 0, sizeof off, D->stream) != hipSuccess ||
+      hipMemcpyAsync(d_cs, chunk_start.data(), chunk_start.size() * sizeof(uint16_t), hipMemcpyHostToDevice,
+                     D->stream) != hipSuccess ||
+      hipMemcpyAsync(d_rlo, run_lo.data(), run_lo.size(), hipMemcpyHostToDevice, D->stream) != hipSuccess ||
+      hipMemcpyAsync(d_rhi, run_hi.data(), run_hi.size(), hipMemcpyHostToDevice, D->stream) != hipSuccess ||
       hipEventRecord(ev[0], D->stream) != hipSuccess) {
     cleanup();
     return BDEG_E_DEVICE;
@@ -623,15 +679,25 @@ int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32
   a.W = W;
   a.items = d_items;
   a.n_items = (uint32_t)items.size();
-  a.units = d_units;
+  a.units = d_raw;
   a.cap_units = (uint32_t)cap_units;
+  a.bucket_off = d_off;
+  a.bucket_cnt = d_bcnt;
+  a.chunk_start = d_cs;
+  a.run_lo = d_rlo;
+  a.run_hi = d_rhi;
   a.cnt = d_pc;
+  uint32_t bcnt[64] = {0};
   rc = launch_prune(D->stream, a);
+  if (!rc) rc = launch_prune_compact(D->stream, d_raw, d_units, d_off, d_bcnt, W - 1, N - 1, (uint32_t)cap_units);
   if (!rc && (hipEventRecord(ev[1], D->stream) != hipSuccess ||
               hipMemcpyAsync(&pc, d_pc, sizeof pc, hipMemcpyDeviceToHost, D->stream) != hipSuccess ||
+              hipMemcpyAsync(bcnt, d_bcnt, sizeof bcnt, hipMemcpyDeviceToHost, D->stream) != hipSuccess ||
               hipStreamSynchronize(D->stream) != hipSuccess))
     rc = BDEG_E_DEVICE;
-  if (!rc && pc.overflow) rc = BDEG_E_STATE; // cannot happen: the buffer holds every unit
+  if (!rc && pc.overflow) rc = BDEG_E_STATE; // cannot happen: every bucket holds all its units
+  pc.units = 0;
+  for (int c = W - 1; c < N; c++) pc.units += bcnt[c];
   if (!rc) {
     LaunchShape shape = job.shape;
     shape.single = single_group(N);

@@ -149,12 +149,19 @@ struct PruneArgs {
   int N, K, W;        // W = K + 1 - |prefix|
   const uint64_t *items;
   uint32_t n_items;   // prefixes (vertex masks), all with K + 1 - W points
-  Tile *units;        // out: one unit per next element below each prefix kept
-  uint32_t cap_units;
+  Tile *units;        // out: for each prefix F kept and next element c, the units
+  uint32_t cap_units; //   (F + c, run) for the runs of chunk c, in bucket c:
+  const uint32_t *bucket_off; // units[bucket_off[c] + (running count)]
+  uint32_t *bucket_cnt;
+  const uint16_t *chunk_start; // chunk c: runs chunk_start[c] .. chunk_start[c + 1] - 1
+  const uint8_t *run_lo, *run_hi; // run [run_lo, run_hi] of the element after c
   PruneCounters *cnt;
 };
 // One wavefront per prefix: eliminate it, test it, emit the units below it.
 int launch_prune(void *stream, const PruneArgs &a);
+// Gather buckets c_hi .. c_lo of the bucketed units into one list (in order).
+int launch_prune_compact(void *stream, const Tile *in, Tile *out, const uint32_t *off, const uint32_t *cnt, int c_lo,
+                         int c_hi, uint32_t cap);
 
 // ------------------------------------------------------------ kernels (kernels.hip)
 // enumeration kernel variants

@@ -35,9 +35,7 @@
 namespace bdeg {
 namespace dev {
 
-constexpr int PK = BDEG_MAX_K;    // widest point set
-constexpr int PW = PRUNE_WMAX;    // widest prefix state
-constexpr int PM = PRUNE_WMAX + 1; // rows of the simplex
+constexpr int PK = BDEG_MAX_K; // widest point set
 constexpr uint32_t PLOW31 = 0x7FFFFFFFu;
 
 __device__ __forceinline__ int32_t prl32(int32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
@@ -60,23 +58,28 @@ __device__ __forceinline__ double bp64f(double v, int src) {
 }
 
 // State of the float simplex (lanes 0..W hold the rows).
+template <int W>
 struct Lp {
-  double inv[PW];  // row scales (uniform)
-  double binv[PM]; // lane i <= W: row i of the basis inverse
-  double xb;       // lane i <= W: basic value of row i
-  double pi[PM];   // duals (uniform)
+  static constexpr int M = W + 1;
+  double inv[W];  // row scales (uniform)
+  double binv[M]; // lane i <= W: row i of the basis inverse
+  double xb;      // lane i <= W: basic value of row i
+  double pi[M];   // duals (uniform)
   int32_t mybasis; // lane i <= W: lane of row i's basic variable, -1 for an artificial
   uint64_t basic;  // basic lanes
 };
 
 // Lane j's column of the constraint matrix: (r_j / scale, 1).
-__device__ __forceinline__ double col_entry(const Lp &lp, const int32_t (&s)[PW], int q, int W) {
-  return q < W ? (double)s[q] * lp.inv[q] : 1.0;
+template <int W>
+__device__ __forceinline__ double col_entry(const Lp<W> &lp, const int32_t (&s)[W], int q) {
+  return q < W ? (double)s[q] * lp.inv[q < W ? q : 0] : 1.0;
 }
 
 // One pivot: lane e enters, row lv leaves; col (lane i: row i of the entering
 // column in the current basis), de = its reduced cost.
-__device__ __forceinline__ void lp_pivot(Lp &lp, int lv, int e, double col, double de) {
+template <int W>
+__device__ __forceinline__ void lp_pivot(Lp<W> &lp, int lv, int e, double col, double de) {
+  constexpr int PM = W + 1;
   const int lane = (int)(threadIdx.x & 63);
   const double rp = 1.0 / rl64f(col, lv);
   double prow[PM];
@@ -95,11 +98,13 @@ __device__ __forceinline__ void lp_pivot(Lp &lp, int lv, int e, double col, doub
 }
 
 // The entering column of lane e in the current basis, row i in lane i.
-__device__ __forceinline__ double entering_col(const Lp &lp, const int32_t (&s)[PW], int e, int W) {
+template <int W>
+__device__ __forceinline__ double entering_col(const Lp<W> &lp, const int32_t (&s)[W], int e) {
+  constexpr int PM = W + 1;
   double col = 0.0;
 #pragma unroll
   for (int q = 0; q < PM; q++) {
-    const double ae = q < W ? (double)prl32(s[q], e) * lp.inv[q] : (q == W ? 1.0 : 0.0);
+    const double ae = q < W ? (double)prl32(s[q < W ? q : 0], e) * lp.inv[q < W ? q : 0] : 1.0;
     col += lp.binv[q] * ae;
   }
   return col;
@@ -107,19 +112,20 @@ __device__ __forceinline__ double entering_col(const Lp &lp, const int32_t (&s)[
 
 // True when the prefix state (s, H1, H0, prev) with W columns lies in no lower
 // face (certified).  lanes: the points outside the prefix.
-__device__ bool prefix_not_face(const int32_t (&s)[PW], int32_t H1s, int32_t H0s, int32_t prevs, int W,
-                                uint64_t lanes, uint32_t *pivots) {
+template <int W>
+__device__ __forceinline__ bool prefix_not_face(const int32_t (&s)[W], int32_t H1s, int32_t H0s, int32_t prevs,
+                                                uint64_t lanes, uint32_t *pivots) {
   constexpr double TOL = 1e-9;
   constexpr uint32_t UMAX = 0xFFFFFFFFu;
-  const int M = W + 1;
-  const int max_it = 4 * M + 12;
+  constexpr int M = W + 1, PW = W, PM = W + 1;
+  constexpr int max_it = 4 * M + 12;
   const int lane = (int)(threadIdx.x & 63);
   const bool in = (lanes >> lane) & 1;
-  Lp lp;
+  Lp<W> lp;
   // scales: a_j = (r_j / max|r|, 1) per row, cost_j = sign(prev) h_j / max|h|
 #pragma unroll
   for (int q = 0; q < PW; q++) {
-    const float m = __uint_as_float(~wave_umin(~(in && q < W ? __float_as_uint(fabsf((float)s[q])) : 0u)));
+    const float m = __uint_as_float(~wave_umin(~(in ? __float_as_uint(fabsf((float)s[q])) : 0u)));
     lp.inv[q] = m > 0.f ? 1.0 / (double)m : 1.0;
   }
   const double h = (double)H1s * 2147483648.0 + (double)(uint32_t)H0s;
@@ -140,7 +146,7 @@ __device__ bool prefix_not_face(const int32_t (&s)[PW], int32_t H1s, int32_t H0s
     double d = phase2 ? cost : 0.0;
 #pragma unroll
     for (int q = 0; q < PM; q++)
-      if (q <= W) d -= lp.pi[q] * col_entry(lp, s, q, W);
+      d -= lp.pi[q] * col_entry(lp, s, q);
     const bool cand = in && !((lp.basic >> lane) & 1) && d < -TOL;
     const uint32_t key = cand ? fkey((float)d) : UMAX;
     const uint32_t kmin = wave_umin(key);
@@ -160,7 +166,7 @@ __device__ bool prefix_not_face(const int32_t (&s)[PW], int32_t H1s, int32_t H0s
         double v = 0.0;
 #pragma unroll
         for (int q = 0; q < PM; q++)
-          if (q < M) v += rl64f(lp.binv[q], i) * col_entry(lp, s, q, W);
+          v += rl64f(lp.binv[q], i) * col_entry(lp, s, q);
         const bool ok = in && !((lp.basic >> lane) & 1) && fabs(v) > TOL;
         const uint32_t mk = ok ? ~__float_as_uint(fabsf((float)v)) : UMAX;
         const uint32_t best = wave_umin(mk);
@@ -169,7 +175,7 @@ __device__ bool prefix_not_face(const int32_t (&s)[PW], int32_t H1s, int32_t H0s
           continue;
         }
         const int e = __builtin_ctzll(pbal(mk == best));
-        lp_pivot(lp, i, e, entering_col(lp, s, e, W), 0.0);
+        lp_pivot(lp, i, e, entering_col(lp, s, e), 0.0);
         it++;
       }
       if (stuck) break;
@@ -189,7 +195,7 @@ __device__ bool prefix_not_face(const int32_t (&s)[PW], int32_t H1s, int32_t H0s
     if (++it > max_it) break;
     const int e = __builtin_ctzll(pbal(key == kmin));
     const double de = rl64f(d, e);
-    const double col = entering_col(lp, s, e, W);
+    const double col = entering_col(lp, s, e);
     // ratio test over the rows; among equal ratios an artificial leaves first
     const bool rowc = lane < M && col > TOL;
     const uint32_t tk = rowc ? fkey((float)lp.xb * __builtin_amdgcn_rcpf((float)col)) : UMAX;
@@ -201,10 +207,7 @@ __device__ bool prefix_not_face(const int32_t (&s)[PW], int32_t H1s, int32_t H0s
   }
   *pivots += (uint32_t)it;
   // the optimum sum lambda c is pi . b = pi[W] (b = e_W)
-  double piW = lp.pi[0];
-#pragma unroll
-  for (int q = 1; q < PM; q++)
-    if (q == W) piW = lp.pi[q];
+  const double piW = lp.pi[W];
   if (stuck || !phase2 || it > max_it || !(piW < -1e-12)) return false;
   // exact certificate; a0 = the basic lane with the largest weight
   int i0 = 0;
@@ -260,10 +263,12 @@ __device__ bool prefix_not_face(const int32_t (&s)[PW], int32_t H1s, int32_t H0s
   return ok && (dpos ? sa < 0 : sa > 0);
 }
 
+template <int W>
 __global__ void __launch_bounds__(256) prune_kernel(PruneArgs a) {
+  constexpr int PW = W;
   const int lane = (int)(threadIdx.x & 63);
   const bool valid = lane < a.N;
-  const int K = a.K, W = a.W;
+  const int K = a.K;
   const int d = K + 1 - W;   // prefix size
   const int lo_next = K - d; // the next element leaves room for K - d more below it
   uint32_t n_deg = 0, n_cut = 0, n_piv = 0;
@@ -344,30 +349,31 @@ __global__ void __launch_bounds__(256) prune_kernel(PruneArgs a) {
     }
     const uint64_t lanes = pbal(valid) & ~S;
     uint32_t its = 0;
-    const bool cut = prefix_not_face(s, H1, H0, prev, W, lanes, &its);
+    const bool cut = prefix_not_face<W>(s, H1, H0, prev, lanes, &its);
     n_piv += its;
     if (cut) {
       n_cut++;
       continue;
     }
-    // units: one per next element c in [lo_next, e - 1]
-    const int n = e - lo_next;
-    if (n <= 0) continue;
-    const uint32_t got = atomicAdd(&a.cnt->units, lane == 0 ? (uint32_t)n : 0u);
-    const uint32_t pos0 = (uint32_t)prl32((int32_t)got, 0);
+    // units: lane c in [lo_next, e - 1] writes the runs of chunk c (mask F + c,
+    // a run of the element after c) into bucket c
     if (lane >= lo_next && lane < e) {
-      const uint32_t pos = pos0 + (uint32_t)(lane - lo_next);
-      if (pos < a.cap_units) {
-        Tile t;
-        t.mask = S;
-        t.sys = 0;
-        t.c_lo = (uint8_t)lane;
-        t.c_hi = (uint8_t)lane;
-        t.pad = 0;
-        a.units[pos] = t;
+      const int r0 = a.chunk_start[lane], r1 = a.chunk_start[lane + 1];
+      uint32_t pos = a.bucket_off[lane] + atomicAdd(&a.bucket_cnt[lane], (uint32_t)(r1 - r0));
+      for (int r = r0; r < r1; r++, pos++) {
+        if (pos < a.cap_units) {
+          Tile t;
+          t.mask = W == 1 ? S : S | (1ull << lane); // (W = 1: the unit F, run [c, c])
+          t.sys = 0;
+          t.c_lo = a.run_lo[r];
+          t.c_hi = a.run_hi[r];
+          t.pad = 0;
+          a.units[pos] = t;
+        } else {
+          atomicOr(&a.cnt->overflow, 1u);
+        }
       }
     }
-    if (lane == 0 && pos0 + (uint32_t)n > a.cap_units) atomicOr(&a.cnt->overflow, 1u);
   }
   if (lane == 0) {
     if (n_deg) atomicAdd(&a.cnt->degenerate, n_deg);
@@ -376,20 +382,58 @@ __global__ void __launch_bounds__(256) prune_kernel(PruneArgs a) {
   }
 }
 
+// Gather the buckets, largest next element (largest subtrees) first, into one
+// list: thread i moves unit i of the bucketed array.
+__global__ void __launch_bounds__(256) prune_compact_kernel(const Tile *in, Tile *out, const uint32_t *off,
+                                                            const uint32_t *cnt, int c_lo, int c_hi, uint32_t cap) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= cap) return;
+  uint32_t start = 0;
+  for (int c = c_hi; c >= c_lo; c--) {
+    if (i >= off[c] && i - off[c] < cnt[c]) {
+      out[start + (i - off[c])] = in[i];
+      return;
+    }
+    start += cnt[c];
+  }
+}
+
 } // namespace dev
 
 int launch_prune(void *stream, const PruneArgs &a) {
   if (a.W < 1 || a.W > PRUNE_WMAX || a.K < a.W || a.K > BDEG_MAX_K || a.N > 64) return BDEG_E_ARG;
   if (a.n_items == 0) return BDEG_OK;
+  const void *f = nullptr;
+  switch (a.W) {
+    case 1: f = (const void *)dev::prune_kernel<1>; break;
+    case 2: f = (const void *)dev::prune_kernel<2>; break;
+    case 3: f = (const void *)dev::prune_kernel<3>; break;
+    case 4: f = (const void *)dev::prune_kernel<4>; break;
+    case 5: f = (const void *)dev::prune_kernel<5>; break;
+    case 6: f = (const void *)dev::prune_kernel<6>; break;
+    case 7: f = (const void *)dev::prune_kernel<7>; break;
+    default: f = (const void *)dev::prune_kernel<8>; break;
+  }
   int per_cu = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)dev::prune_kernel, 256, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0) != hipSuccess ||
       hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu <= 0)
     return BDEG_E_DEVICE;
   uint64_t blocks = (uint64_t)per_cu * cus;
   const uint64_t need = ((uint64_t)a.n_items + 3) / 4;
   if (blocks > need) blocks = need;
-  hipLaunchKernelGGL(dev::prune_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a);
+  void *args[] = {(void *)&a};
+  if (hipLaunchKernel(f, dim3((unsigned)blocks), dim3(256), args, 0, (hipStream_t)stream) != hipSuccess)
+    return BDEG_E_DEVICE;
+  return hipGetLastError() == hipSuccess ? BDEG_OK : BDEG_E_DEVICE;
+}
+
+int launch_prune_compact(void *stream, const Tile *in, Tile *out, const uint32_t *off, const uint32_t *cnt, int c_lo,
+                         int c_hi, uint32_t cap) {
+  if (cap == 0) return BDEG_OK;
+  if (c_lo < 0 || c_hi > 63 || c_lo > c_hi) return BDEG_E_ARG;
+  hipLaunchKernelGGL(dev::prune_compact_kernel, dim3((cap + 255) / 256), dim3(256), 0, (hipStream_t)stream, in, out,
+                     off, cnt, c_lo, c_hi, cap);
   return hipGetLastError() == hipSuccess ? BDEG_OK : BDEG_E_DEVICE;
 }
 
