@@ -94,6 +94,32 @@ def walk_leg(bd, gen, m: int, k: int) -> dict:
             "alu_frac": r["cells"] * walk_ops_per_cell(N, r["k"]) / wt / PEAK_ALU}
 
 
+def prune_leg(bd, gen, name: str, reps: int = 5) -> dict:
+    """The prefix-pruned enumeration on a bench system (its points and the
+    lifting of its plain solve), device time of both phases, checked against
+    the plain path's volume."""
+    s = {"headline": gen.cfg2_system, "large36": gen.cfg4_system}[name]()
+    sub = bd.subdivision(s.A, seed=1, lift_bits=s.lift_bits, cap=0)
+    P, H = sub["points"], sub["heights"]
+    bd.nvol_points_pruned(P, H)
+    dev, wall = [], []
+    for _ in range(reps):
+        t = time.perf_counter()
+        g = bd.nvol_points_pruned(P, H)
+        wall.append(time.perf_counter() - t)
+        assert g["nvol"] == sub["nvol"] and not g["tie"], (g, sub["nvol"])
+        dev.append(g["stats"]["filter_ms"] + g["stats"]["enum_ms"])
+    st = g["stats"]
+    N, k = P.shape
+    cand = math.comb(N, k + 1)
+    ms = sum(dev) / len(dev)
+    log(f"[bench] pruned {name}: {ms:.3f} ms device (filter {st['filter_ms']:.3f}, enumeration {st['enum_ms']:.3f}), "
+        f"{st['pruned']} of {st['prefixes']} prefixes pruned")
+    return {"device_ms": round(ms, 4), "filter_ms": round(st["filter_ms"], 4), "enum_ms": round(st["enum_ms"], 4),
+            "wall_ms": round(1e3 * sum(wall) / len(wall), 4), "cand_per_s": cand / (ms * 1e-3),
+            "width": st["width"], "prefixes": st["prefixes"], "pruned": st["pruned"], "units": st["units"]}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -166,6 +192,8 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a dispatch of known "
                          "traffic, for scaling hardware byte counters)")
+    ap.add_argument("--pruned", default="", choices=["", "headline", "large36"],
+                    help="run only the prefix-pruned enumeration of this system and print its figures")
     ap.add_argument("--walk", default="",
                     help="M,K: run only the cell walk on the Table 4 system W_{M,K} and print its figures")
     a = ap.parse_args()
@@ -189,6 +217,10 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {a.calibrate_copy_mib} MiB read + {a.calibrate_copy_mib} MiB written")
         del src, dst
+
+    if a.pruned:
+        print(json.dumps({"pruned": a.pruned, **prune_leg(bd, gen, a.pruned)}), flush=True)
+        return
 
     if a.walk:
         m, k = (int(x) for x in a.walk.split(","))
@@ -287,6 +319,10 @@ def main():
         extra["large36_kernel_ms"] = round(st4["kernel_ms"], 3)
         extra["large36_cand_per_s"] = cand4 / (st4["total_ms"] * 1e-3)
         log(f"[bench] n=36 k=10: nvol={r4['nvol']} kernel {st4['kernel_ms']:.2f} ms")
+
+        # the prefix-pruned enumeration of the headline and n = 36 systems
+        for name in ("headline", "large36"):
+            extra.update({f"pruned_{name}_{key}": v for key, v in prune_leg(bd, gen, name).items()})
 
         # the cell walk on the largest Table 4 system, W_{4,5} (k = 22, N = 61)
         extra.update({f"walk_w45_{key}": v for key, v in walk_leg(bd, gen, 4, 5).items()})
