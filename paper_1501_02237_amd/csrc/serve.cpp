@@ -48,6 +48,18 @@ constexpr int MAX_SLOTS = 4096;
 constexpr uint32_t STEP_TILES_MAX = 32768;
 constexpr uint64_t STEP_CANDIDATES = 24000000; // quantum of one step
 constexpr uint64_t UNIT_COST = 2048;           // work-unit size cap for served requests
+
+constexpr size_t LIGHT_LOAD = 8; // requests queued or running below which units are small
+
+// Work-unit size of a request.  Under light load (few requests queued or
+// running) as for a plain solve: the request alone spread over the resident
+// wavefronts (at least 256 candidates), so that a small request is not one
+// wavefront's work; otherwise UNIT_COST, so that a step of a full device
+// carries its whole quantum within the step's unit limit.
+uint64_t request_unit_cost(int N, int k, bool light) {
+  if (!light) return UNIT_COST;
+  return std::min<uint64_t>(UNIT_COST, choose_max_cost(binom_u64(N, k + 1), default_waves(k, k, 4)));
+}
 constexpr size_t PROLOGUE_THREADS = 8;         // host prologue workers for a burst of submissions
 
 using Clock = std::chrono::steady_clock;
@@ -110,6 +122,7 @@ struct bdeg_server {
   bool admit(Request *r);
   void start_attempt(Request *r);
   void finish(Request *r, int status);
+  bool light = true; // few requests queued or running (set before each admission round)
 };
 
 int bdeg_server::setup_device() {
@@ -185,7 +198,7 @@ void bdeg_server::start_attempt(Request *r) {
   // units are taken round-robin across requests in small steps, so their
   // order within a request does not matter: no sort
   std::vector<TileC> tc;
-  tiles_full(d.N, d.k, (uint32_t)r->slot, UNIT_COST, tc);
+  tiles_full(d.N, d.k, (uint32_t)r->slot, request_unit_cost(d.N, d.k, light), tc);
   r->tiles.resize(tc.size());
   for (size_t i = 0; i < tc.size(); i++) r->tiles[i] = tc[i].t;
   r->next = 0;
@@ -195,7 +208,7 @@ void bdeg_server::start_attempt(Request *r) {
 // heights, descriptor, partial sum) and its share of the step's unit buffer.
 bool bdeg_server::admit(Request *r) {
   const uint64_t cand = binom_u64(r->hs.N, r->hs.k + 1);
-  const size_t units_est = (size_t)(cand / UNIT_COST + r->hs.N);
+  const size_t units_est = (size_t)(cand / request_unit_cost(r->hs.N, r->hs.k, light) + r->hs.N);
   const size_t need = SLOT_BYTES + std::min<size_t>(units_est, STEP_TILES_MAX) * sizeof(Tile);
   if (free_slots.empty() || used + need > budget) return false;
   r->slot = free_slots.back();
@@ -258,6 +271,7 @@ void bdeg_server::run() {
     fresh.clear();
     // 2. admission in arrival order (relift still holds requests whose tied
     //    lifting was redrawn at the end of the previous step)
+    light = active.size() + waiting.size() < LIGHT_LOAD;
     while (!waiting.empty() && admit(waiting.front())) {
       relift.push_back(waiting.front());
       waiting.pop_front();
@@ -313,8 +327,19 @@ void bdeg_server::run() {
       if (hipMemcpyAsync(d_tiles, h_tiles, nt * sizeof(Tile), hipMemcpyHostToDevice, stream) != hipSuccess)
         rc = BDEG_E_DEVICE;
       if (!rc) rc = launch_clear(stream, nullptr, 0, d_cnt, NB);
-      if (!rc && hipEventRecord(step_ready, stream) != hipSuccess) rc = BDEG_E_DEVICE;
-      for (int k = 1; k <= BDEG_MAX_K && !rc; k++) {
+      int groups = 0;
+      for (int b = 0; b < NB; b++) groups += !byk[b].empty();
+      if (!rc && groups == 1) { // one group: launch it on the engine stream itself
+        for (int b = 0; b < NB && !rc; b++) {
+          if (byk[b].empty()) continue;
+          LaunchShape shape;
+          shape.single = b % GROUP_SLOTS == group_slot(true);
+          rc = launch_enumerate(stream, d_sys, d_pts, d_hts, d_tiles + start[b], (uint32_t)byk[b].size(), d_acc,
+                                d_cnt + b, b / GROUP_SLOTS, b / GROUP_SLOTS, shape);
+        }
+      }
+      if (!rc && groups > 1 && hipEventRecord(step_ready, stream) != hipSuccess) rc = BDEG_E_DEVICE;
+      for (int k = 1; k <= BDEG_MAX_K && !rc && groups > 1; k++) {
         bool any = false;
         for (int gs = 0; gs < GROUP_SLOTS; gs++) any |= !byk[k * GROUP_SLOTS + gs].empty();
         if (!any) continue;
@@ -337,7 +362,9 @@ void bdeg_server::run() {
     }
     // 4. partial sums of all active slots
     static DevCounters cnt[(BDEG_MAX_K + 1) * GROUP_SLOTS];
-    if (!rc && hipMemcpyAsync(h_acc, d_acc, max_slots * sizeof(SysAcc), hipMemcpyDeviceToHost, stream) != hipSuccess)
+    int used = 0; // slots up to the highest one in use
+    for (Request *r : active) used = std::max(used, r->slot + 1);
+    if (!rc && hipMemcpyAsync(h_acc, d_acc, used * sizeof(SysAcc), hipMemcpyDeviceToHost, stream) != hipSuccess)
       rc = BDEG_E_DEVICE;
     if (!rc && hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, stream) != hipSuccess)
       rc = BDEG_E_DEVICE;
