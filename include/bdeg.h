@@ -234,7 +234,7 @@ int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32
  *   points, heights  as for bdeg_nvol_points (k <= BDEG_PIVOT_MAX_K);
  *   start_mask       a cell (k+1 points) that is a lower facet for `heights`;
  *                    BDEG_E_ARG when it is not;
- *   cell_masks [cap] the cells in discovery order (cap = 0: none copied);
+ *   cell_masks [cap] the cells, in no particular order (cap = 0: none copied);
  *   *n_cells, *nvol  number of cells and the sum of their normalized volumes;
  *   *tie             a non-generic lower face was met (results then invalid).
  * Device memory grows with the number of cells (16 bytes per cell in flight,

@@ -110,6 +110,8 @@ struct PivotCounters {
   uint32_t pad;
   unsigned long long vol_lo, vol_hi; // sum of |D| over processed cells (128-bit)
   unsigned long long cells;          // processed cells
+  uint32_t chained;                  // chain steps claimed in the current level
+  uint32_t pad2;
 };
 
 struct PivotArgs {
@@ -122,6 +124,7 @@ struct PivotArgs {
   uint32_t cap_list;
   uint64_t *table;    // hash set of cells (0 = empty), power-of-two size
   uint64_t table_mask;
+  uint32_t chain_budget; // chain steps the list's room allows in this level
   PivotCounters *cnt;
 };
 typedef void (*PivotFn)(PivotArgs);
@@ -129,8 +132,9 @@ typedef void (*PivotFn)(PivotArgs);
 // one wavefront of a persistent grid of `blocks` blocks of 4 wavefronts.
 int launch_pivot(void *stream, const PivotArgs &a, int k, int blocks);
 int max_pivot_blocks(int k);
-// Insert list[0, n) into the (cleared) hash set a.table.
-int launch_pivot_rehash(void *stream, const PivotArgs &a, uint32_t n);
+// Insert the nonzero entries of old[0, n_old) (the previous set) into the
+// (cleared) hash set a.table.
+int launch_pivot_rehash(void *stream, const PivotArgs &a, const uint64_t *old, uint64_t n_old);
 
 // ------------------------------------------------------------ prefix pruning (kernels_prune.hip)
 constexpr int PRUNE_WMAX = 8; // widest prefix state tested (free spatial columns)

@@ -56,17 +56,20 @@ int launch_pivot(void *stream, const PivotArgs &a, int k, int blocks) {
 }
 
 namespace dev {
-// Rebuild the hash set from the work list after the set has grown: one
-// thread per listed cell (the list holds no duplicates).
-__global__ void __launch_bounds__(256) pivot_rehash_kernel(PivotArgs a, uint32_t n) {
-  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-  if (i < n) (void)set_insert(a, a.list[i]);
+// Rebuild the hash set after it has grown: one thread per slot of the old
+// set (every cell, including the chained ones that never enter the list).
+__global__ void __launch_bounds__(256) pivot_rehash_kernel(PivotArgs a, const uint64_t *old, uint64_t n_old) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  if (i < n_old && old[i]) (void)set_insert(a, old[i]);
 }
 } // namespace dev
 
-int launch_pivot_rehash(void *stream, const PivotArgs &a, uint32_t n) {
-  if (n == 0) return BDEG_OK;
-  hipLaunchKernelGGL(dev::pivot_rehash_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, a, n);
+int launch_pivot_rehash(void *stream, const PivotArgs &a, const uint64_t *old, uint64_t n_old) {
+  if (n_old == 0) return BDEG_OK;
+  const uint64_t blocks = (n_old + 255) / 256;
+  if (blocks > 0x7FFFFFFFull) return BDEG_E_ARG;
+  hipLaunchKernelGGL(dev::pivot_rehash_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a, old,
+                     n_old);
   return hipGetLastError() == hipSuccess ? BDEG_OK : BDEG_E_DEVICE;
 }
 

@@ -4,8 +4,9 @@
 // The walk starts from a cell that is a lower facet for the given heights and
 // visits the cells breadth-first: every level is one persistent launch over
 // the cells discovered by the previous level; the host reads the work-list
-// length between levels (no device-side waiting).  A full hash set or work
-// list doubles both and restarts; a tie is returned to the caller.
+// length between levels (no device-side waiting).  A wavefront also follows
+// a chain of new neighbours by single pivots; those cells skip the list.  A
+// tie is returned to the caller.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -53,7 +54,8 @@ struct WalkResult {
 };
 
 // Make room for `need` cells: a larger work list (the listed cells copied)
-// and a hash set of twice that many slots rebuilt from the list, so the set's
+// and a hash set of twice that many slots rebuilt from the old set (it holds
+// every cell, also the chained ones that never enter the list), so the set's
 // load stays at most 1/2.
 int grow(Device *D, WalkBuffers &b, PivotArgs &a, uint64_t need, uint32_t tail) {
   uint64_t cap = b.cap ? b.cap : (1ull << 20);
@@ -66,24 +68,28 @@ int grow(Device *D, WalkBuffers &b, PivotArgs &a, uint64_t need, uint32_t tail) 
     (void)hipFree(list);
     return BDEG_E_NOMEM;
   }
+  a.list = list;
+  a.cap_list = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull);
+  a.table = table;
+  a.table_mask = 2 * cap - 1;
+  int rc = BDEG_OK;
   if (hipMemsetAsync(table, 0, 2 * cap * sizeof(uint64_t), D->stream) != hipSuccess ||
       (tail && hipMemcpyAsync(list, b.list, tail * sizeof(uint64_t), hipMemcpyDeviceToDevice, D->stream) !=
-                   hipSuccess) ||
-      hipStreamSynchronize(D->stream) != hipSuccess) {
+                   hipSuccess))
+    rc = BDEG_E_DEVICE;
+  if (!rc && b.table) rc = launch_pivot_rehash(D->stream, a, b.table, 2 * b.cap);
+  if (!rc && hipStreamSynchronize(D->stream) != hipSuccess) rc = BDEG_E_DEVICE;
+  if (rc) {
     (void)hipFree(list);
     (void)hipFree(table);
-    return BDEG_E_DEVICE;
+    return rc;
   }
   if (b.list) (void)hipFree(b.list);
   if (b.table) (void)hipFree(b.table);
   b.list = list;
   b.table = table;
   b.cap = cap;
-  a.list = list;
-  a.cap_list = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull);
-  a.table = table;
-  a.table_mask = 2 * cap - 1;
-  return launch_pivot_rehash(D->stream, a, tail);
+  return BDEG_OK;
 }
 
 // One walk from `start`, breadth first.  Before each level the list and the
@@ -110,6 +116,9 @@ int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k,
     a.N = N;
     a.cnt = b.cnt;
     // a fresh, empty list and set of `room` cells holding the start cell
+    if (b.list) (void)hipFree(b.list);
+    if (b.table) (void)hipFree(b.table);
+    b.list = b.table = nullptr;
     b.cap = 0;
     int rc = grow(D, b, a, room, 0);
     if (rc) return rc;
@@ -121,15 +130,25 @@ int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k,
         hipMemcpyAsync(b.cnt, &c0, sizeof c0, hipMemcpyHostToDevice, D->stream) != hipSuccess)
       return BDEG_E_DEVICE;
     uint32_t first = 0, count = 1;
+    uint64_t in_set = 1; // cells in the set: the listed ones and the chained ones
     PivotCounters c{};
     bool regrow = false;
     while (count > 0) {
-      rc = grow(D, b, a, (uint64_t)first + count + (uint64_t)count * (k + 1), first + count);
+      // every cell processed in this level (listed or chained) inserts at most
+      // k + 1 new cells into the set and the list; room for the level's own
+      // cells and as many again for chained ones, and chain steps limited to
+      // what is left, keep the list within its capacity and the set at most
+      // half full
+      const uint64_t tail0 = (uint64_t)first + count;
+      rc = grow(D, b, a, in_set + 2 * (uint64_t)count * (k + 1), (uint32_t)tail0);
       if (rc) return rc;
       a.first = first;
       a.count = count;
+      const uint64_t steps = (b.cap - in_set) / (uint64_t)(k + 1);
+      a.chain_budget = steps > count ? (uint32_t)std::min<uint64_t>(steps - count, 0xFFFFFFFFull) : 0u;
       const uint32_t zero = 0;
-      if (hipMemcpyAsync(&b.cnt->next, &zero, sizeof zero, hipMemcpyHostToDevice, D->stream) != hipSuccess)
+      if (hipMemcpyAsync(&b.cnt->next, &zero, sizeof zero, hipMemcpyHostToDevice, D->stream) != hipSuccess ||
+          hipMemcpyAsync(&b.cnt->chained, &zero, sizeof zero, hipMemcpyHostToDevice, D->stream) != hipSuccess)
         return BDEG_E_DEVICE;
       rc = launch_pivot(D->stream, a, k, blocks);
       if (rc) return rc;
@@ -145,6 +164,7 @@ int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k,
         out.tie = true;
         return BDEG_OK;
       }
+      in_set += (uint64_t)(c.tail - tail0) + std::min<uint64_t>(c.chained, a.chain_budget);
       first += count;
       count = c.tail - first;
     }
@@ -155,11 +175,13 @@ int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k,
     out.tie = false;
     out.nvol = ((u128)c.vol_hi << 64) | c.vol_lo;
     out.cells = c.cells;
-    if (cells_out) {
-      cells_out->resize(c.tail);
-      if (c.tail && hipMemcpy(cells_out->data(), b.list, c.tail * sizeof(uint64_t), hipMemcpyDeviceToHost) !=
-                        hipSuccess)
+    if (cells_out) { // every cell is in the hash set (chained cells skip the list)
+      std::vector<uint64_t> slots(2 * b.cap);
+      if (hipMemcpy(slots.data(), b.table, slots.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
         return BDEG_E_DEVICE;
+      cells_out->clear();
+      for (uint64_t m : slots)
+        if (m) cells_out->push_back(m);
     }
     return BDEG_OK;
   }

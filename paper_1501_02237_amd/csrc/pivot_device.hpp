@@ -39,6 +39,7 @@ namespace dev {
 
 constexpr uint32_t PIVOT_LOW31 = 0x7FFFFFFFu;
 constexpr int PIVOT_MAX_PROBE = 4096;
+constexpr int PIVOT_MAX_CHAIN = 4; // chain steps after one claimed cell (longer chains serialise a level)
 
 __device__ __forceinline__ int32_t prl(int32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 __device__ __forceinline__ int32_t pbp(int32_t v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
@@ -129,48 +130,94 @@ __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
       if (lane == 0) atomicOr(&a.cnt->flags, PIVOT_ERR_STATE);
       continue;
     }
-    const int32_t D = prev;
-    const bool neg = D < 0;
-    // height above the cell's hyperplane, times |D|
-    const int64_t s_raw = (int64_t)H1 * ((int64_t)1 << 31) + (int64_t)(uint32_t)H0;
-    const int64_t S = neg ? -s_raw : s_raw;
-    const bool other = valid && !in_cell;
-    const uint64_t below = pballot(other && S < 0), on = pballot(other && S == 0);
-    if (below) { // not a lower facet: the start cell was wrong, or a bug
-      if (lane == 0) atomicOr(&a.cnt->flags, PIVOT_ERR_STATE);
-      continue;
-    }
-    if (on && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE);
-    vol += (uint64_t)(neg ? -(int64_t)D : (int64_t)D);
-    cells++;
-    // barycentric coordinate of the base point, times D
-    int64_t sum = 0;
-#pragma unroll
-    for (int t = 0; t < K; t++) sum += x[t];
-    const int64_t c0 = (int64_t)D - sum;
-    // facets: opposite the point pivoted at step t (row t), then opposite v0;
-    // lane t keeps the neighbour across facet t
-    uint64_t mine = 0;
-#pragma unroll
-    for (int t = 0; t <= K; t++) {
-      const int64_t c = t < K ? (int64_t)x[t] : c0;
-      const int64_t cs = neg ? -c : c; // lambda * |D|
-      const bool beyond = other && cs < 0;
-      const RatioMin rm = ratio_min(beyond ? S : 0, beyond ? (int32_t)(-cs) : 0);
-      const int u = rm.lane;
-      if ((rm.lanes & (rm.lanes - 1)) && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE); // equal minima
-      if (u >= 0) { // (none: the facet is on the boundary of the hull)
-        const int v = t < K ? pivlane[t] : v0;
-        if (lane == t) mine = (C & ~(1ull << v)) | (1ull << u);
+    // the cell, then a chain of neighbours: each one is reached by one pivot
+    // of the tableau instead of a new elimination
+    int32_t D = prev;
+    uint64_t Cc = C;
+    for (int hop = 0;; hop++) {
+      const bool neg = D < 0;
+      const bool in_c = (Cc >> lane) & 1;
+      // height above the cell's hyperplane, times |D|
+      const int64_t s_raw = (int64_t)H1 * ((int64_t)1 << 31) + (int64_t)(uint32_t)H0;
+      const int64_t S = neg ? -s_raw : s_raw;
+      const bool other = valid && !in_c;
+      const uint64_t below = pballot(other && S < 0), on = pballot(other && S == 0);
+      if (below) { // not a lower facet: the start cell was wrong, or a bug
+        if (lane == 0) atomicOr(&a.cnt->flags, PIVOT_ERR_STATE);
+        break;
       }
-    }
-    // lane t inserts the neighbour across facet t: all probes in one round
-    if (mine && set_insert(a, mine)) {
-      const uint32_t pos = atomicAdd(&a.cnt->tail, 1u);
-      if (pos < a.cap_list)
-        a.list[pos] = mine;
-      else
-        atomicOr(&a.cnt->flags, PIVOT_ERR_FULL);
+      if (on && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE);
+      vol += (uint64_t)(neg ? -(int64_t)D : (int64_t)D);
+      cells++;
+      // barycentric coordinate of the base point, times D
+      int64_t sum = 0;
+#pragma unroll
+      for (int t = 0; t < K; t++) sum += x[t];
+      const int64_t c0 = (int64_t)D - sum;
+      // facets: opposite the point pivoted at step t (row t), then opposite v0;
+      // lane t keeps the neighbour across facet t
+      uint64_t mine = 0;
+#pragma unroll
+      for (int t = 0; t <= K; t++) {
+        const int64_t c = t < K ? (int64_t)x[t] : c0;
+        const int64_t cs = neg ? -c : c; // lambda * |D|
+        const bool beyond = other && cs < 0;
+        const RatioMin rm = ratio_min(beyond ? S : 0, beyond ? (int32_t)(-cs) : 0);
+        const int u = rm.lane;
+        if ((rm.lanes & (rm.lanes - 1)) && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE); // equal minima
+        if (u >= 0) { // (none: the facet is on the boundary of the hull)
+          const int v = t < K ? pivlane[t] : v0;
+          if (lane == t) mine = (Cc & ~(1ull << v)) | (1ull << u);
+        }
+      }
+      // lane t inserts the neighbour across facet t: all probes in one round
+      const bool fresh = mine && set_insert(a, mine);
+      // the chain goes on into the first new neighbour across a facet t < k
+      // (same base point) while the level's room allows
+      const uint64_t fr = pballot(fresh) & ((1ull << K) - 1);
+      int tc = -1;
+      if (fr && hop < PIVOT_MAX_CHAIN) {
+        const uint32_t claim = atomicAdd(&a.cnt->chained, lane == 0 ? 1u : 0u);
+        if ((uint32_t)prl((int32_t)claim, 0) < a.chain_budget) tc = __builtin_ctzll(fr);
+      }
+      if (fresh && lane != tc) {
+        const uint32_t pos = atomicAdd(&a.cnt->tail, 1u);
+        if (pos < a.cap_list)
+          a.list[pos] = mine;
+        else
+          atomicOr(&a.cnt->flags, PIVOT_ERR_FULL);
+      }
+      if (tc < 0) break;
+      // pivot: the point of row tc leaves, u enters; with e = x_tc(u),
+      // x_r <- (e x_r - x_r(u) x_tc) / D for r != tc, row tc stays, D <- e
+      const uint64_t nb = ((uint64_t)(uint32_t)prl((int32_t)(mine >> 32), tc) << 32) |
+                          (uint32_t)prl((int32_t)(uint32_t)mine, tc);
+      const int u = __builtin_ctzll(nb & ~Cc);
+      int32_t pc[K];
+#pragma unroll
+      for (int r = 0; r < K; r++) pc[r] = prl(x[r], u);
+      const int32_t ph1 = prl(H1, u), ph0 = prl(H0, u);
+      int32_t e = 1, xt = 0;
+#pragma unroll
+      for (int r = 0; r < K; r++)
+        if (r == tc) {
+          e = pc[r];
+          xt = x[r];
+        }
+      const Div dv = make_div(D);
+#pragma unroll
+      for (int r = 0; r < K; r++)
+        if (r != tc) x[r] = exdiv32((int64_t)e * x[r] - (int64_t)pc[r] * xt, dv);
+      const int64_t A = (int64_t)e * H1 - (int64_t)ph1 * xt;
+      const int64_t B = (int64_t)e * H0 - (int64_t)ph0 * xt;
+      const int64_t h = exdiv_split(A, B, dv);
+      H1 = (int32_t)(h >> 31);
+      H0 = (int32_t)((uint32_t)h & PIVOT_LOW31);
+#pragma unroll
+      for (int r = 0; r < K; r++)
+        if (r == tc) pivlane[r] = u;
+      D = e;
+      Cc = nb;
     }
   }
   // the wave's tallies (uniform values) in one update
