@@ -99,6 +99,7 @@ struct CellSink {
 
 // ------------------------------------------------------------ cell walk (kernels_pivot*.hip)
 constexpr int PIVOT_MAX_K = BDEG_PIVOT_MAX_K; // deepest k of the cell walk
+constexpr int PIVOT_CHAIN_STEPS = 4;           // chain steps after one claimed cell
 constexpr uint32_t PIVOT_TIE = 1;       // a non-generic lower face was met
 constexpr uint32_t PIVOT_ERR_FULL = 2;  // hash set or work list out of room
 constexpr uint32_t PIVOT_ERR_STATE = 4; // a listed cell is not a lower facet (bad start cell)

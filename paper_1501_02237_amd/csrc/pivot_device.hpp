@@ -39,7 +39,7 @@ namespace dev {
 
 constexpr uint32_t PIVOT_LOW31 = 0x7FFFFFFFu;
 constexpr int PIVOT_MAX_PROBE = 4096;
-constexpr int PIVOT_MAX_CHAIN = 4; // chain steps after one claimed cell (longer chains serialise a level)
+
 
 __device__ __forceinline__ int32_t prl(int32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 __device__ __forceinline__ int32_t pbp(int32_t v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
       // (same base point) while the level's room allows
       const uint64_t fr = pballot(fresh) & ((1ull << K) - 1);
       int tc = -1;
-      if (fr && hop < PIVOT_MAX_CHAIN) {
+      if (fr && hop < PIVOT_CHAIN_STEPS) { // (longer chains serialise a level)
         const uint32_t claim = atomicAdd(&a.cnt->chained, lane == 0 ? 1u : 0u);
         if ((uint32_t)prl((int32_t)claim, 0) < a.chain_budget) tc = __builtin_ctzll(fr);
       }
