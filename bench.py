@@ -67,6 +67,23 @@ def ops_per_launch(stats: dict, N: int, k: int) -> float:
     return N * (8.0 * sp + 24.0 * ht) + 20.0 * (N - k - 1) * stats["leaves"]
 
 
+def walk_leg(bd, gen, m: int, k: int) -> dict:
+    """The cell walk on the Table 4 system W_{m,k}, end to end (prologue,
+    allocation, every level) after a warm-up walk, checked against the
+    paper's degree."""
+    with open(os.path.join(ROOT, "tests", "golden", "paper_values.json")) as fh:
+        deg = json.load(fh)["table4_degrees"][f"{m},{k}"]
+    A = gen.master_space_matrix(m, k)
+    bd.degree_pivot(gen.master_space_matrix(3, 4), seed=5, lift_bits=20)
+    t = time.perf_counter()
+    r = bd.degree_pivot(A, seed=5, lift_bits=20)
+    wt = time.perf_counter() - t
+    assert r["status"] == 0 and r["comps"] * r["nvol"] == deg, (r, deg)
+    N = len(A[0]) + 1
+    log(f"[bench] walk W_{m},{k}: k={r['k']} N={N} {r['cells']} cells in {wt:.3f} s")
+    return {"s": round(wt, 4), "cells": r["cells"], "cells_per_s": r["cells"] / wt}
+
+
 def prune_leg(bd, gen, name: str, reps: int = 5) -> dict:
     """The prefix-pruned enumeration on a bench system (its points and the
     lifting of its plain solve), device time of both phases, checked against
