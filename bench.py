@@ -34,12 +34,13 @@ PEAK_ALU = 256 * 4 * 16 * 2.4e9  # 32-bit integer VALU lane-ops/s: CUs x SIMDs x
 # per dispatch, mean of the timed dispatches), each scaled by what the counter
 # reads for a device copy of known size in the same run (FETCH_SIZE reads half
 # of the 256 MiB copied, WRITE_SIZE all of it).  Valid only for the kernel
-# source the counters were taken on; any change to it makes `traffic` null.
+# source and the work-unit sizing (runtime.cpp) the counters were taken on; any
+# change to them makes `traffic` null.
 TRAFFIC = {
-    "sources": ("enum_device.hpp", "exact_div.hpp", "kernels_k8.hip"),
-    "sha256": "89055dff530742876f0d991de2a9fc10d410e623985bd9f5645bfbd9187be976",
-    "fetch_kib": 4503.61, "fetch_scale": 262144.0 / 131089.0,
-    "write_kib": 1966.16, "write_scale": 262144.0 / 262144.0,
+    "sources": ("enum_device.hpp", "exact_div.hpp", "kernels_k8.hip", "runtime.cpp"),
+    "sha256": "00452258d5fa41f239a67f9e509b6263406f858c65afa30c39c12c6f00d05c73",
+    "fetch_kib": 1720.19, "fetch_scale": 262144.0 / 131093.0,
+    "write_kib": 1007.72, "write_scale": 262144.0 / 262144.0,
 }
 
 

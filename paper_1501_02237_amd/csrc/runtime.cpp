@@ -50,11 +50,10 @@ int default_waves(int kmin, int kmax, int waves_per_block) {
   return blocks > 0 ? blocks * waves_per_block : 1024;
 }
 
-// Subtree size cap: about 16 work units per resident wavefront, never below
-// 256 candidates (a unit re-derives its prefix, which costs a few levels).
-uint64_t choose_max_cost(uint64_t total, int waves) {
+// Subtree size cap (a unit re-derives its prefix, which costs a few levels).
+uint64_t choose_max_cost(uint64_t total, int waves, uint64_t floor) {
   uint64_t per = total / ((uint64_t)(waves > 0 ? waves : 1) * 16);
-  return per < 256 ? 256 : per;
+  return per < floor ? floor : per;
 }
 
 

@@ -82,7 +82,12 @@ int job_launch(Job &job, hipStream_t stream, hipEvent_t ev_kernel_start = nullpt
 // Copy accumulators back (synchronous on stream).
 int job_collect(Job &job, hipStream_t stream, std::vector<SysAcc> &acc, DevCounters *cnt);
 
-uint64_t choose_max_cost(uint64_t total_candidates, int waves);
+// Work-unit size cap: about 16 units per resident wavefront, never below
+// `floor` candidates.  Throughput work uses the default floor (fewer, longer
+// units: less prefix re-derivation per candidate); latency work (a lone small
+// request) passes a smaller one to spread over more wavefronts.
+constexpr uint64_t UNIT_FLOOR = 512;
+uint64_t choose_max_cost(uint64_t total_candidates, int waves, uint64_t floor = UNIT_FLOOR);
 int default_waves(int kmin, int kmax, int waves_per_block);
 
 } // namespace bdeg

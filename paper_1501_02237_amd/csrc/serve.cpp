@@ -50,15 +50,17 @@ constexpr uint64_t STEP_CANDIDATES = 24000000; // quantum of one step
 constexpr uint64_t UNIT_COST = 2048;           // work-unit size cap for served requests
 
 constexpr size_t LIGHT_LOAD = 8; // requests queued or running below which units are small
+constexpr uint64_t LIGHT_UNIT_FLOOR = 256; // smallest unit under light load
 
 // Work-unit size of a request.  Under light load (few requests queued or
-// running) as for a plain solve: the request alone spread over the resident
-// wavefronts (at least 256 candidates), so that a small request is not one
+// running) the request alone is spread over the resident wavefronts in units
+// of at least LIGHT_UNIT_FLOOR candidates (below a plain solve's floor: here
+// latency counts, not throughput), so that a small request is not one
 // wavefront's work; otherwise UNIT_COST, so that a step of a full device
 // carries its whole quantum within the step's unit limit.
 uint64_t request_unit_cost(int N, int k, bool light) {
   if (!light) return UNIT_COST;
-  return std::min<uint64_t>(UNIT_COST, choose_max_cost(binom_u64(N, k + 1), default_waves(k, k, 4)));
+  return std::min<uint64_t>(UNIT_COST, choose_max_cost(binom_u64(N, k + 1), default_waves(k, k, 4), LIGHT_UNIT_FLOOR));
 }
 constexpr size_t PROLOGUE_THREADS = 8;         // host prologue workers for a burst of submissions
 
