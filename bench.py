@@ -38,8 +38,8 @@ PEAK_ALU = 256 * 4 * 16 * 2.4e9  # 32-bit integer VALU lane-ops/s: CUs x SIMDs x
 # change to them makes `traffic` null.
 TRAFFIC = {
     "sources": ("enum_device.hpp", "exact_div.hpp", "kernels_k8.hip", "runtime.cpp"),
-    "sha256": "00452258d5fa41f239a67f9e509b6263406f858c65afa30c39c12c6f00d05c73",
-    "fetch_kib": 1720.19, "fetch_scale": 262144.0 / 131093.0,
+    "sha256": "73a4be853bd6743a1ab318521506a6d09ec3df87f67d1eb167422ab9667a791e",
+    "fetch_kib": 1731.33, "fetch_scale": 262144.0 / 131092.0,
     "write_kib": 1007.72, "write_scale": 262144.0 / 262144.0,
 }
 

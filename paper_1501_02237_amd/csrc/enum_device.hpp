@@ -210,60 +210,67 @@ __device__ __forceinline__ int32_t fetch_diag(const CX &cx, int32_t v, int c, in
 }
 
 // Leaf test in sign-normalised form.  Each lane keeps a candidate view of its
-// point j at the current ridge: a_j = sign(prev) |sigma_j| and
-// b_j = sign(prev) sign(sigma_j) h_j (both height halves).  For candidate c
-// (D = sigma_c) and point j,
+// point j at the current ridge: a_j = sign(prev) |sigma_j| and the negated
+// b_j = sign(prev) sign(sigma_j) h_j (both height halves, stored as -b_j so
+// that each half of the cross product is a chain of multiply-adds).  For
+// candidate c (D = sigma_c) and point j,
 //     t' = a_c h_j - b_c sigma_j = sign(D prev) (sigma_c h_j - h_c sigma_j),
 // whose sign is that of D s_j: point j lies below the candidate's hyperplane
 // exactly when t' < 0.  With h = H1 2^31 + H0, t' = 2^31 C + lo, 0 <= lo < 2^31,
-// so t' < 0 exactly when C < 0, and t' = 0 exactly when C = lo = 0.
+// so t' < 0 exactly when C < 0, and t' = 0 exactly when C = lo = 0.  With
+// |a|, |sigma| < 2^31, 0 <= H0 < 2^31 and |H1| < 2^29 (height minors < 2^60)
+// every partial sum below stays under 2^63.
 struct View {
-  int32_t a, b1, b0;
+  int32_t a, nb1, nb0;
 };
 __device__ __forceinline__ View cand_view(int32_t sig, int32_t H1, int32_t H0, bool prevneg) {
   const int32_t mag = sig < 0 ? -sig : sig;
   const bool f = (sig < 0) != prevneg;
   View v;
   v.a = prevneg ? -mag : mag;
-  v.b1 = f ? -H1 : H1;
-  v.b0 = f ? -H0 : H0;
+  v.nb1 = f ? H1 : -H1;
+  v.nb0 = f ? H0 : -H0;
   return v;
 }
 struct Cross {
   int64_t C;
   uint32_t lo;
 };
-__device__ __forceinline__ Cross cross_view(int32_t a, int32_t b1, int32_t b0, int32_t sig, int32_t H1,
+// t' = a h - b sigma from a, -b (both halves) and this lane's (sigma, H1, H0)
+__device__ __forceinline__ Cross cross_view(int32_t a, int32_t nb1, int32_t nb0, int32_t sig, int32_t H1,
                                             int32_t H0) {
-  const int64_t A = (int64_t)a * H1 - (int64_t)b1 * sig;
-  const int64_t B = (int64_t)a * H0 - (int64_t)b0 * sig;
+  const int64_t B = (int64_t)a * H0 + (int64_t)nb0 * sig;
   Cross r;
-  r.C = A + (B >> 31);
+  r.C = (int64_t)a * H1 + ((int64_t)nb1 * sig + (B >> 31));
   r.lo = (uint32_t)B & LOW31;
   return r;
 }
 
 // Decide one leaf step: group q tests its candidate, point cand - q.
-//   m_neg lanes whose point lies strictly below their group's candidate hyperplane
+//   m_neg lanes holding a real point strictly below their group's candidate
+//         hyperplane.  Only the padding lanes need masking out: the chosen
+//         points and the group's ridge point have vanishing residuals, and the
+//         candidate's own cross product cancels, so their t' is exactly 0.
 //   t     this lane's t' (for the zero test, needed only when a group survives)
-//   m_sc  groups whose candidate exists and has D != 0 (all of their lanes set)
-//   excl  lanes outside the test: padding, chosen points, the candidate
+//   has   top bits of the groups whose candidate exists and has D != 0
+//   excl  lanes outside the zero test (padding, chosen points, ridge points);
+//         the candidates' own lanes are added only when a group survives
 // A group with a point strictly below the candidate's hyperplane rejects
 // (the common case, decided for all groups with a handful of scalar mask
 // operations); otherwise a point on the hyperplane is a tie and none is a
 // lower facet.  For the cell list: `fixed` holds the points every group
 // shares and, when ridge >= 0, group q's ridge adds point ridge - q.
 template <class CX>
-__device__ __forceinline__ void decide(CX &cx, uint64_t m_neg, const Cross &t, uint64_t m_sc, uint64_t excl,
+__device__ __forceinline__ void decide(CX &cx, uint64_t m_neg, const Cross &t, uint64_t has, uint64_t excl,
                                        int32_t sig, int cand, uint64_t fixed, int ridge) {
-  const uint64_t has = m_sc & cx.top_bits;
   if constexpr (CX::stats) {
     cx.leaves += (uint32_t)__builtin_popcountll(has);
     cx.lsteps++;
     cx.lempty += has == 0;
   }
-  const uint64_t ok = has & ~any_group(cx, m_neg & ~excl);
+  const uint64_t ok = has & ~any_group(cx, m_neg);
   if (ok == 0) return;
+  excl |= diag_lanes(cx, cand);
   const uint64_t m_nz = ballot((t.C != 0) | (t.lo != 0));
   const uint64_t zero = ok & any_group(cx, ~(m_nz | excl));
   const int npl = cx.npl();
@@ -304,15 +311,15 @@ __device__ __forceinline__ void leaves_uniform(CX &cx, const St<1> &st, int hi_c
     uint64_t todo = ballot(sig != 0) & cx.valid_lanes & range;
     if (!charge(cx, __builtin_popcountll(todo))) return;
     while (todo) {
-      const int c0 = 63 - __builtin_clzll(todo);
+      const int c0 = __builtin_ctzll(todo); // any order: the tallies are sums
       todo &= ~(1ull << c0);
       // unnormalised t = sigma_c h_j - h_c sigma_j, its sign flipped by the
       // (wave-uniform) sign of D prev
       const int32_t sc = rl32(sig, c0);
-      const Cross t = cross_view(sc, rl32(H1, c0), rl32(H0, c0), sig, H1, H0);
+      const Cross t = cross_view(sc, -rl32(H1, c0), -rl32(H0, c0), sig, H1, H0);
       const bool flip = (sc < 0) != prevneg;
       const uint64_t m_neg = ballot(((t.C != 0) | (t.lo != 0)) && ((t.C < 0) != flip));
-      decide(cx, m_neg, t, ~0ull, excl | (1ull << c0), sig, c0, fixed, -1);
+      decide(cx, m_neg & cx.valid_lanes, t, cx.top_bits, excl, sig, c0, fixed, -1);
     }
     return;
   }
@@ -323,8 +330,9 @@ __device__ __forceinline__ void leaves_uniform(CX &cx, const St<1> &st, int hi_c
     const bool ok = cg >= lo_c;
     const int src = cx.g * cx.npad() + (ok ? cg : 0);
     const int32_t a = fetch_diag(cx, v.a, c0, src);
-    const Cross t = cross_view(a, fetch_diag(cx, v.b1, c0, src), fetch_diag(cx, v.b0, c0, src), sig, H1, H0);
-    decide(cx, ballot(t.C < 0), t, ballot(ok && a != 0), excl | diag_lanes(cx, c0), sig, c0, fixed, -1);
+    const Cross t = cross_view(a, fetch_diag(cx, v.nb1, c0, src), fetch_diag(cx, v.nb0, c0, src), sig, H1, H0);
+    decide(cx, ballot(t.C < 0) & cx.valid_lanes, t, ballot(ok) & ballot(a != 0) & cx.top_bits, excl, sig, c0, fixed,
+           -1);
   }
 }
 
@@ -468,6 +476,7 @@ struct Level {
             cx.rsteps++;
           }
           if (!m_alive) continue;
+          const uint64_t alive_top = m_alive & cx.top_bits;
           const uint64_t excl = ~cx.valid_lanes | cx.chosen_rep | diag_lanes(cx, c);
           const uint64_t fixed = CX::emit ? (cx.chosen_rep & group0_mask(cx)) : 0ull;
           // candidates: group q tests cc - q for cc = c-1 .. 0, visiting only
@@ -484,15 +493,16 @@ struct Level {
           todo &= (1ull << c) - 1;
           if (!charge(cx, __builtin_popcountll(todo))) continue;
           while (todo) {
-            const int cc = 63 - __builtin_clzll(todo);
+            const int cc = __builtin_ctzll(todo); // any order: the tallies are sums
             todo &= ~(1ull << cc);
             // cc < g: no candidate in group g (the fetch reads a lane of the
-            // group below, in range, and is masked out of m_sc)
+            // group below, in range, and is masked out of `has`)
             const int src2 = base + cc;
             const int32_t a = bp32(v.a, src2);
-            const Cross t = cross_view(a, bp32(v.b1, src2), bp32(v.b0, src2), sig, H1, H0);
-            const uint64_t m_sc = ballot(cc >= cx.g && alive && a != 0);
-            decide(cx, ballot(t.C < 0), t, m_sc, excl | diag_lanes(cx, cc), sig, cc, fixed, c);
+            const Cross t = cross_view(a, bp32(v.nb1, src2), bp32(v.nb0, src2), sig, H1, H0);
+            // (two ballots: a ballot of the combined condition would go through a VGPR)
+            const uint64_t has = ballot(a != 0) & ballot(cc >= cx.g) & alive_top;
+            decide(cx, ballot(t.C < 0) & cx.valid_lanes, t, has, excl, sig, cc, fixed, c);
           }
         }
       }
