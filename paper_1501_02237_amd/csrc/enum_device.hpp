@@ -116,9 +116,11 @@ struct Ctx {
   // registers they would be copied at every level of the loop nest
   struct Tally *tally;
   // watchdog: loop steps left for this unit (a budget derived from the unit's
-  // candidate count); running out abandons the unit and reports a device
-  // error, so no wavefront can loop without end
-  uint32_t left;
+  // candidate count); running out (left <= 0) abandons the unit and reports a
+  // device error, so no wavefront can loop without end.  Signed, so that a
+  // charge is a scalar subtract and a sign test (an unsigned saturating
+  // subtract would go through a vector register)
+  int32_t left;
   // work counters of the profiling variant
   uint32_t leaves, ridges, inner, sp_upd, pruned, rsteps, lsteps, lempty;
   // cell list of the emitting variant
@@ -144,7 +146,7 @@ __device__ __forceinline__ void emit_cell(CX &cx, uint64_t vertices) {
 
 template <class CX>
 __device__ __forceinline__ bool step_ok(CX &cx) {
-  if (cx.left == 0) return false;
+  if (cx.left <= 0) return false;
   cx.left--;
   return true;
 }
@@ -155,12 +157,8 @@ __device__ __forceinline__ bool step_ok(CX &cx) {
 template <class CX>
 __device__ __forceinline__ bool charge(CX &cx, int n) {
   if (n <= 0) return true;
-  if ((uint32_t)n >= cx.left) {
-    cx.left = 0;
-    return false;
-  }
-  cx.left -= (uint32_t)n;
-  return true;
+  cx.left -= n;
+  return cx.left > 0;
 }
 
 __device__ __forceinline__ uint64_t binom_dev(int n, int r) {
@@ -457,7 +455,6 @@ struct Level {
           const int32_t r0 = bp32(st.s[0], src), r1 = bp32(st.s[1], src);
           const int32_t h1c = bp32(st.H1, src), h0c = bp32(st.H0, src);
           const bool p0 = r0 != 0;
-          const bool alive = gok && (p0 || r1 != 0);
           const int32_t piv = p0 ? r0 : (r1 != 0 ? r1 : 1);
           const int32_t rco = p0 ? r1 : r0;
           const int32_t rjp = p0 ? st.s[0] : st.s[1], so = p0 ? st.s[1] : st.s[0];
@@ -467,7 +464,8 @@ struct Level {
           const int64_t h = exdiv_split(A, B, dv);
           const int32_t H1 = (int32_t)(h >> 31), H0 = (int32_t)((uint32_t)h & LOW31);
           const bool pivneg = piv < 0;
-          const uint64_t m_alive = ballot(alive);
+          // (ballots of single compares, ANDed in scalar registers)
+          const uint64_t m_alive = ballot(gok) & ballot((r0 | r1) != 0);
           const int ngr = min(G, c - lo_c + 1);
           if constexpr (S) {
             const uint32_t n_alive = (uint32_t)__builtin_popcountll(m_alive & cx.rep_unit);
@@ -483,13 +481,16 @@ struct Level {
           // the cc for which some live group's point cc - q has D != 0 (lane
           // j of group q stands for cc = j + q; chosen and ridge points have
           // a zero residual and drop out by themselves)
-          const uint64_t nzl = ballot(alive && sig != 0) & cx.valid_lanes;
+          const uint64_t nzl = m_alive & ballot(sig != 0) & cx.valid_lanes;
           const View v = cand_view(sig, H1, H0, pivneg);
           const int base = cx.g * cx.npad() - cx.g; // lane of point cc - g is base + cc
           const int npl = cx.npl();
           const uint64_t gm0 = (1ull << cx.npad()) - 1;
           uint64_t todo = 0;
-          for (int q = 0; q < G; q++) todo |= ((nzl >> (q << npl)) & gm0) << q;
+          if (G == 2) // the common case (17 to 32 points), without a loop
+            todo = (nzl & gm0) | ((nzl >> 32) << 1);
+          else
+            for (int q = 0; q < G; q++) todo |= ((nzl >> (q << npl)) & gm0) << q;
           todo &= (1ull << c) - 1;
           if (!charge(cx, __builtin_popcountll(todo))) continue;
           while (todo) {
@@ -598,7 +599,7 @@ __device__ __forceinline__ void run_unit(const Tile &tl, const SysDesc &sd, cons
     // candidate is charged at most once per depth: k + 1 steps suffice
     const uint64_t cand = unit_candidates(sd.k, tl.mask, tl.c_lo, tl.c_hi);
     const uint64_t b = cand * (uint64_t)(sd.k + 3) + 256;
-    cx.left = b > 0xFFFFFFF0ull ? 0xFFFFFFF0u : (uint32_t)b;
+    cx.left = b > 0x7FFFFFF0ull ? 0x7FFFFFF0 : (int32_t)b;
   }
   switch (sd.k) {
 #define BDEG_CASE(KK)                                      \
@@ -613,7 +614,7 @@ __device__ __forceinline__ void run_unit(const Tile &tl, const SysDesc &sd, cons
     default:
       break;
   }
-  const bool abandoned = cx.left == 0;
+  const bool abandoned = cx.left <= 0;
   if (lane == 0 && abandoned) atomicOr(&cnt->error, 1u);
   if (lane == 0 && !abandoned) {
     const unsigned long long sum = tally->acc;
