@@ -311,13 +311,13 @@ __device__ __forceinline__ void leaves_uniform(CX &cx, const St<1> &st, int hi_c
     while (todo) {
       const int c0 = __builtin_ctzll(todo); // any order: the tallies are sums
       todo &= ~(1ull << c0);
-      // unnormalised t = sigma_c h_j - h_c sigma_j, its sign flipped by the
-      // (wave-uniform) sign of D prev
-      const int32_t sc = rl32(sig, c0);
-      const Cross t = cross_view(sc, -rl32(H1, c0), -rl32(H0, c0), sig, H1, H0);
+      // t' = s (sigma_c h_j - h_c sigma_j) with s the (wave-uniform) sign of
+      // D prev, folded into the candidate's scalar values: a = s sigma_c and
+      // -b = -s h_c (|sigma_c| < 2^31, so the negations are exact)
+      const int32_t sc = rl32(sig, c0), h1c = rl32(H1, c0), h0c = rl32(H0, c0);
       const bool flip = (sc < 0) != prevneg;
-      const uint64_t m_neg = ballot(((t.C != 0) | (t.lo != 0)) && ((t.C < 0) != flip));
-      decide(cx, m_neg & cx.valid_lanes, t, cx.top_bits, excl, sig, c0, fixed, -1);
+      const Cross t = cross_view(flip ? -sc : sc, flip ? h1c : -h1c, flip ? h0c : -h0c, sig, H1, H0);
+      decide(cx, ballot(t.C < 0) & cx.valid_lanes, t, cx.top_bits, excl, sig, c0, fixed, -1);
     }
     return;
   }
