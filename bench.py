@@ -38,8 +38,8 @@ PEAK_ALU = 256 * 4 * 16 * 2.4e9  # 32-bit integer VALU lane-ops/s: CUs x SIMDs x
 # change to them makes `traffic` null.
 TRAFFIC = {
     "sources": ("enum_device.hpp", "exact_div.hpp", "kernels_k8.hip", "runtime.cpp"),
-    "sha256": "407c2d6747c3550af54ef9ec4c777ae360b9ca9cc0da770cb1247c60fcdff613",
-    "fetch_kib": 1790.08, "fetch_scale": 262144.0 / 131093.0,
+    "sha256": "77ab8e04773518e8f2f090c59294e01d57ee4332f6983736d1162abb25f8214a",
+    "fetch_kib": 1756.28, "fetch_scale": 262144.0 / 131088.0,
     "write_kib": 1007.72, "write_scale": 262144.0 / 262144.0,
 }
 

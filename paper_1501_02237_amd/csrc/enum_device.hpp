@@ -245,10 +245,10 @@ __device__ __forceinline__ Cross cross_view(int32_t a, int32_t nb1, int32_t nb0,
 }
 
 // Decide one leaf step: group q tests its candidate, point cand - q.
-//   m_neg lanes holding a real point strictly below their group's candidate
-//         hyperplane.  Only the padding lanes need masking out: the chosen
-//         points and the group's ridge point have vanishing residuals, and the
-//         candidate's own cross product cancels, so their t' is exactly 0.
+//   m_neg lanes strictly below their group's candidate hyperplane.  No lane
+//         needs masking out: padding lanes and the chosen points and the
+//         group's ridge point have vanishing residuals, and the candidate's own
+//         cross product cancels, so their t' is exactly 0.
 //   t     this lane's t' (for the zero test, needed only when a group survives)
 //   has   top bits of the groups whose candidate exists and has D != 0
 //   excl  lanes outside the zero test (padding, chosen points, ridge points);
@@ -317,7 +317,7 @@ __device__ __forceinline__ void leaves_uniform(CX &cx, const St<1> &st, int hi_c
       const int32_t sc = rl32(sig, c0), h1c = rl32(H1, c0), h0c = rl32(H0, c0);
       const bool flip = (sc < 0) != prevneg;
       const Cross t = cross_view(flip ? -sc : sc, flip ? h1c : -h1c, flip ? h0c : -h0c, sig, H1, H0);
-      decide(cx, ballot(t.C < 0) & cx.valid_lanes, t, cx.top_bits, excl, sig, c0, fixed, -1);
+      decide(cx, ballot(t.C < 0), t, cx.top_bits, excl, sig, c0, fixed, -1);
     }
     return;
   }
@@ -329,7 +329,7 @@ __device__ __forceinline__ void leaves_uniform(CX &cx, const St<1> &st, int hi_c
     const int src = cx.g * cx.npad() + (ok ? cg : 0);
     const int32_t a = fetch_diag(cx, v.a, c0, src);
     const Cross t = cross_view(a, fetch_diag(cx, v.nb1, c0, src), fetch_diag(cx, v.nb0, c0, src), sig, H1, H0);
-    decide(cx, ballot(t.C < 0) & cx.valid_lanes, t, ballot(ok) & ballot(a != 0) & cx.top_bits, excl, sig, c0, fixed,
+    decide(cx, ballot(t.C < 0), t, ballot(ok) & ballot(a != 0) & cx.top_bits, excl, sig, c0, fixed,
            -1);
   }
 }
@@ -503,7 +503,7 @@ struct Level {
             const Cross t = cross_view(a, bp32(v.nb1, src2), bp32(v.nb0, src2), sig, H1, H0);
             // (two ballots: a ballot of the combined condition would go through a VGPR)
             const uint64_t has = ballot(a != 0) & ballot(cc >= cx.g) & alive_top;
-            decide(cx, ballot(t.C < 0) & cx.valid_lanes, t, has, excl, sig, cc, fixed, c);
+            decide(cx, ballot(t.C < 0), t, has, excl, sig, cc, fixed, c);
           }
         }
       }
@@ -528,10 +528,13 @@ __device__ __forceinline__ void process_tile(CX &cx, const SysDesc &sd, const in
   const int base = 63 - __builtin_clzll(cx.mask);
   const int64_t wb = (int64_t)(((uint64_t)(uint32_t)rl32((int32_t)(uint32_t)((uint64_t)w >> 32), base) << 32) |
                                (uint32_t)rl32((int32_t)(uint32_t)w, base));
-  const int64_t h0 = w - wb;
+  // padding lanes start from a zero row: every residual derived from it (a
+  // combination of the lane's own entries) stays exactly zero, so their t'
+  // is 0 and the strict test never needs to mask them
+  const int64_t h0 = valid ? w - wb : 0;
   St<K> st;
 #pragma unroll
-  for (int i = 0; i < K; i++) st.s[i] = P[i] - rl32(P[i], base);
+  for (int i = 0; i < K; i++) st.s[i] = valid ? P[i] - rl32(P[i], base) : 0;
   st.H1 = (int32_t)(h0 >> 31);
   st.H0 = (int32_t)((uint32_t)h0 & LOW31);
   st.prev = 1;
