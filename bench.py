@@ -38,8 +38,8 @@ PEAK_ALU = 256 * 4 * 16 * 2.4e9  # 32-bit integer VALU lane-ops/s: CUs x SIMDs x
 # change to them makes `traffic` null.
 TRAFFIC = {
     "sources": ("enum_device.hpp", "exact_div.hpp", "kernels_k8.hip", "runtime.cpp"),
-    "sha256": "77ab8e04773518e8f2f090c59294e01d57ee4332f6983736d1162abb25f8214a",
-    "fetch_kib": 1756.28, "fetch_scale": 262144.0 / 131088.0,
+    "sha256": "20ea98be3016088f45bd421e78bb11282f48347af93b79be51e67fa05244ac77",
+    "fetch_kib": 1777.42, "fetch_scale": 262144.0 / 131093.0,
     "write_kib": 1007.72, "write_scale": 262144.0 / 262144.0,
 }
 

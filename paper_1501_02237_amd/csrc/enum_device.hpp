@@ -161,11 +161,25 @@ __device__ __forceinline__ bool charge(CX &cx, int n) {
   return cx.left > 0;
 }
 
+// Binomial coefficients C(n, r), n <= 64, r <= BDEG_MAX_K + 1, as a Pascal
+// triangle built at compile time (a unit's budget needs two per unit; a
+// multiplicative loop would be a chain of 64-bit divisions)
+constexpr int BINOM_R = BDEG_MAX_K + 2;
+struct BinomTable {
+  uint64_t v[65][BINOM_R];
+};
+constexpr BinomTable make_binom_table() {
+  BinomTable t{};
+  for (int n = 0; n <= 64; n++) {
+    t.v[n][0] = 1;
+    for (int r = 1; r < BINOM_R; r++) t.v[n][r] = n == 0 ? 0 : t.v[n - 1][r - 1] + t.v[n - 1][r];
+  }
+  return t;
+}
+static __constant__ BinomTable kBinom = make_binom_table();
 __device__ __forceinline__ uint64_t binom_dev(int n, int r) {
   if (r < 0 || r > n) return 0;
-  uint64_t c = 1;
-  for (int i = 1; i <= r; i++) c = c * (uint64_t)(n - r + i) / (uint64_t)i;
-  return c;
+  return kBinom.v[n][r]; // callers keep n <= 64 and r <= BDEG_MAX_K + 1
 }
 
 // candidates of a work unit (prefix with L elements, lowest e, run [c_lo, c_hi])
