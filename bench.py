@@ -38,8 +38,8 @@ PEAK_ALU = 256 * 4 * 16 * 2.4e9  # 32-bit integer VALU lane-ops/s: CUs x SIMDs x
 # change to them makes `traffic` null.
 TRAFFIC = {
     "sources": ("enum_device.hpp", "exact_div.hpp", "kernels_k8.hip", "runtime.cpp"),
-    "sha256": "20ea98be3016088f45bd421e78bb11282f48347af93b79be51e67fa05244ac77",
-    "fetch_kib": 1777.42, "fetch_scale": 262144.0 / 131093.0,
+    "sha256": "24dbb4a52de4e5af1b2451c2e41be4fd107d4567f7e2a1706dd6ec0e4a50467d",
+    "fetch_kib": 1786.59, "fetch_scale": 262144.0 / 131093.0,
     "write_kib": 1007.72, "write_scale": 262144.0 / 262144.0,
 }
 

@@ -51,8 +51,13 @@ int default_waves(int kmin, int kmax, int waves_per_block) {
 }
 
 // Subtree size cap (a unit re-derives its prefix, which costs a few levels).
+// At most 2^26 candidates per unit, so that a unit's step budget, (k + 3)
+// steps per candidate with k <= 18, stays below the device's signed 32-bit
+// budget count however large the job.
 uint64_t choose_max_cost(uint64_t total, int waves, uint64_t floor) {
+  constexpr uint64_t MAX_UNIT = 1ull << 26;
   uint64_t per = total / ((uint64_t)(waves > 0 ? waves : 1) * 16);
+  if (per > MAX_UNIT) per = MAX_UNIT;
   return per < floor ? floor : per;
 }
 
