@@ -28,7 +28,10 @@ BDEG_E_NOMEM = -6
 BDEG_E_STATE = -7
 BDEG_F_NEEDS_CONSISTENCY = 1
 MAX_N = 63
-MAX_K = 12
+MAX_K = 18
+MAX_ATTEMPTS = 16
+PIVOT_MAX_K = 24
+PRUNE_MAX_PREFIXES = 1 << 24
 U64_MAX = (1 << 64) - 1
 
 
@@ -208,10 +211,15 @@ def nvol_points_pruned(points, heights, width: int = 0) -> dict:
     return dict(nvol=nv.value, tie=bool(tie.value), cells=cells.value, stats=ps.as_dict())
 
 
-def degree_batch(mats, seed: int = 1, lift_bits: int = 20) -> list[dict]:
+def degree_batch(mats, seed: int = 1, lift_bits: int = 20, check: bool = True) -> list[dict]:
+    """Many systems in one device launch; raises on the first failing system's
+    code unless check=False (then every result carries its own status)."""
     cat, m, n = _pack(mats)
     out = (Result * len(m))()
-    lib().bdeg_degree_batch(cat.ctypes.data, m.ctypes.data, n.ctypes.data, len(m), seed & U64_MAX, lift_bits, out)
+    rc = lib().bdeg_degree_batch(cat.ctypes.data, m.ctypes.data, n.ctypes.data, len(m), seed & U64_MAX, lift_bits,
+                                 out)
+    if check and rc != BDEG_OK:
+        raise BdegError(rc, "bdeg_degree_batch")
     return [r.as_dict() for r in out]
 
 

@@ -26,9 +26,9 @@ ARCH = "gfx950"
 def _flags(src: str) -> list[str]:
     f = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]
     f += [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-    if src.startswith(("kernels_pivot", "kernels_prune")):
-        # the work-item claims of the walk and the prefix filter are atomic adds with a per-lane value
-        # (one lane adds 1): a DPP scan instead of a 64-step scalar loop
+    if src.startswith(("kernels_pivot", "kernels_prune", "kernels_k", "kernels_mixed", "kernels_noalloc")):
+        # the work-item claims of the enumeration, the walk and the prefix filter are atomic adds with a
+        # per-lane value (one lane adds 1): a DPP scan instead of a 64-step scalar loop
         f += ["-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP"]
     return f
 

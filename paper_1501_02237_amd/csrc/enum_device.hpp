@@ -674,9 +674,13 @@ enum_kernel(const SysDesc *__restrict__ sys, const int32_t *__restrict__ pts, co
   __shared__ Tally tallies[4]; // one per wavefront of the block (at most 256 threads)
   Tally *tally = &tallies[threadIdx.x >> 6];
   for (;;) {
-    uint32_t t = 0;
-    if (lane == 0) t = atomicAdd(&cnt->next_tile, 1u);
-    t = __builtin_amdgcn_readfirstlane(t);
+    // Every lane takes part in the claim (lane 0 adds one, the others zero)
+    // and lane 0's result is read by index, so the claimed unit is uniform by
+    // construction and no lane-dependent branch surrounds the loop's exit
+    // test (with a lane-0 branch the compiler may split the loop so that
+    // lanes 1..63 wait for a value lane 0 never produces).
+    const uint32_t claim = atomicAdd(&cnt->next_tile, lane == 0 ? 1u : 0u);
+    const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int32_t)claim, 0);
     if (t >= n_tiles) break;
     const Tile tl = tiles[t];
     const SysDesc sd = sys[tl.sys];

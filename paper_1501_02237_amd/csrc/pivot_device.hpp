@@ -84,7 +84,6 @@ __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
     const uint64_t C = a.list[a.first + item];
     const int v0 = __builtin_ctzll(C);
     const bool valid = lane < a.N;
-    const bool in_cell = (C >> lane) & 1;
     // lane j's column: spatial differences and the split height difference
     int32_t x[K];
     int32_t H1 = 0, H0 = 0;

@@ -112,6 +112,7 @@ struct bdeg_server {
   Tile *h_tiles = nullptr;  // pinned
   SysAcc *h_acc = nullptr;  // pinned
   int32_t *h_list = nullptr; // pinned
+  DevCounters *h_cnt = nullptr; // pinned, one block per (k, kernel variant) of a step
   std::vector<SysDesc> h_sys;
   std::vector<int> free_slots;
   std::deque<Request *> waiting;
@@ -140,7 +141,9 @@ int bdeg_server::setup_device() {
     return BDEG_E_NOMEM;
   if (hipHostMalloc((void **)&h_tiles, STEP_TILES_MAX * sizeof(Tile), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&h_acc, max_slots * sizeof(SysAcc), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void **)&h_list, max_slots * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+      hipHostMalloc((void **)&h_list, max_slots * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&h_cnt, (BDEG_MAX_K + 1) * GROUP_SLOTS * sizeof(DevCounters), hipHostMallocDefault) !=
+          hipSuccess)
     return BDEG_E_NOMEM;
   h_sys.assign(max_slots, SysDesc{});
   for (int s = max_slots - 1; s >= 0; s--) free_slots.push_back(s);
@@ -164,6 +167,7 @@ void bdeg_server::release_device() {
   if (h_tiles) (void)hipHostFree(h_tiles);
   if (h_acc) (void)hipHostFree(h_acc);
   if (h_list) (void)hipHostFree(h_list);
+  if (h_cnt) (void)hipHostFree(h_cnt);
   for (int k = 1; k <= BDEG_MAX_K; k++) {
     if (kstream[k]) (void)hipStreamDestroy(kstream[k]);
     if (kdone[k]) (void)hipEventDestroy(kdone[k]);
@@ -180,6 +184,11 @@ void bdeg_server::finish(Request *r, int status) {
   }
   r->res.status = status;
   r->t_done = Clock::now();
+  // the result and the latency stay readable until close; the request's
+  // matrix, points and work units are no longer needed
+  std::vector<int64_t>().swap(r->A);
+  std::vector<int32_t>().swap(r->hs.pts);
+  std::vector<Tile>().swap(r->tiles);
   std::lock_guard<std::mutex> lk(mu);
   r->state = 3;
   cv_done.notify_all();
@@ -363,16 +372,16 @@ void bdeg_server::run() {
       }
     }
     // 4. partial sums of all active slots
-    static DevCounters cnt[(BDEG_MAX_K + 1) * GROUP_SLOTS];
+    constexpr size_t CNT_BYTES = (BDEG_MAX_K + 1) * GROUP_SLOTS * sizeof(DevCounters);
     int used = 0; // slots up to the highest one in use
     for (Request *r : active) used = std::max(used, r->slot + 1);
     if (!rc && hipMemcpyAsync(h_acc, d_acc, used * sizeof(SysAcc), hipMemcpyDeviceToHost, stream) != hipSuccess)
       rc = BDEG_E_DEVICE;
-    if (!rc && hipMemcpyAsync(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, stream) != hipSuccess)
+    if (!rc && hipMemcpyAsync(h_cnt, d_cnt, CNT_BYTES, hipMemcpyDeviceToHost, stream) != hipSuccess)
       rc = BDEG_E_DEVICE;
     if (!rc && hipStreamSynchronize(stream) != hipSuccess) rc = BDEG_E_DEVICE;
     for (int b = 0; b < (BDEG_MAX_K + 1) * GROUP_SLOTS && !rc; b++)
-      if (!byk[b].empty() && cnt[b].error) rc = BDEG_E_DEVICE;
+      if (!byk[b].empty() && h_cnt[b].error) rc = BDEG_E_DEVICE;
     // 5. retire finished requests, relift tied ones
     std::vector<Request *> still;
     for (Request *r : active) {

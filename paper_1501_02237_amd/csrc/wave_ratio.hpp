@@ -1,5 +1,5 @@
-// Exact wave-wide minimum of ratios num / den (num signed, den > 0), shared by
-// the enumeration kernel's ridge test and the cell walk's pivot.
+// Exact wave-wide minimum of ratios num / den (num signed, den > 0), used by
+// the cell walk's pivot (and the DPP minimum by the prefix filter's pricing).
 //
 // The ratios are screened in float first: each lane converts |num| and den
 // without cancellation (both halves of |num| are non-negative), takes the

@@ -23,6 +23,41 @@ def test_library_exports_every_header_symbol():
     assert not missing, missing
 
 
+def test_binding_constants_equal_the_header():
+    """Every numeric #define of include/bdeg.h that the binding repeats has the
+    header's value (the binding parses nothing at run time)."""
+    import re
+
+    src = open(bd.HEADER).read()
+    defs = {}
+    for name, val in re.findall(r"^#define (BDEG_\w+) (.+?)(?:\s*/\*.*)?$", src, flags=re.M):
+        val = val.strip().rstrip("u")
+        val = val.replace("ull", "").replace("(", "").replace(")", "")
+        try:
+            defs[name] = eval(val, {})
+        except Exception:
+            continue
+    binding = {
+        "BDEG_OK": bd.BDEG_OK, "BDEG_PENDING": bd.BDEG_PENDING, "BDEG_E_ARG": bd.BDEG_E_ARG,
+        "BDEG_E_OVERFLOW": bd.BDEG_E_OVERFLOW, "BDEG_E_TOO_LARGE": bd.BDEG_E_TOO_LARGE,
+        "BDEG_E_TIE": bd.BDEG_E_TIE, "BDEG_E_DEVICE": bd.BDEG_E_DEVICE, "BDEG_E_NOMEM": bd.BDEG_E_NOMEM,
+        "BDEG_E_STATE": bd.BDEG_E_STATE, "BDEG_F_NEEDS_CONSISTENCY": bd.BDEG_F_NEEDS_CONSISTENCY,
+        "BDEG_MAX_N": bd.MAX_N, "BDEG_MAX_K": bd.MAX_K, "BDEG_MAX_ATTEMPTS": bd.MAX_ATTEMPTS,
+        "BDEG_PIVOT_MAX_K": bd.PIVOT_MAX_K, "BDEG_PRUNE_MAX_PREFIXES": bd.PRUNE_MAX_PREFIXES,
+    }
+    for name, v in binding.items():
+        assert name in defs, name
+        assert defs[name] == v, (name, defs[name], v)
+
+
+def test_degree_batch_raises_on_a_failing_system():
+    """A system over the size limit fails before any device work: the batch
+    call raises unless asked for per-system statuses (no GPU needed)."""
+    too_wide = np.zeros((1, bd.MAX_N + 1), dtype=np.int64)
+    with pytest.raises(bd.BdegError):
+        bd.degree_batch([too_wide])
+
+
 def test_strerror_covers_codes():
     for c in (0, 1, -1, -2, -3, -4, -5, -6, -7):
         assert bd.strerror(c) and "unknown" not in bd.strerror(c)
