@@ -1,16 +1,20 @@
 """Benchmark: exact candidate simplices decided per second on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu] [--only LEG]
 
 Headline workload (one "step" = one full device pass over one system, inputs
-resident in HBM): the plain quiver-like system n = 28 (20 rows p - q of weight
-2-3, k = 8, N = 29 points, C(29, 9) = 10,015,005 candidates, heights < 2^20).
-A step clears the accumulators, draws the lifting, enumerates and tests every
-candidate and reads the 128-bit volume back (tie redraws included).
+resident in HBM): the large quiver-like system n = 36 (26 rows p - q of
+weight 2-4, k = 10, N = 37 points, C(37, 11) = 854,992,152 candidates,
+heights < 2^24), the largest single-system workload.  A step resets the
+accumulators, draws the lifting, enumerates and tests every candidate, runs
+the (empty) tie-redraw rounds and reads the 128-bit volume back.
 
-Also reported (keys under "extra"): end-to-end plain solves (host prologue +
-copies), the 4096-system batch in one launch vs plain one-by-one solves, the
-n = 36 (k = 10) system, and the serving trace when available.
+Also reported (keys under "extra"): the n = 28 system (k = 8) the same way,
+end-to-end plain solves (host prologue + copies), the 4096-system batch in
+one captured pass vs plain one-by-one solves, the prefix-pruned enumeration,
+the cell walk, and the serving trace.  The oracle leg times the oracle on a
+bounded colex rank slice of the headline system, on all host threads and on
+one.
 
 Prints ONE JSON line.  Only one GPU is used: --gpus above 1 exits.
 """
@@ -29,18 +33,19 @@ sys.path.insert(0, ROOT)
 
 PEAK_ALU = 256 * 4 * 16 * 2.4e9  # 32-bit integer VALU lane-ops/s: CUs x SIMDs x lanes x clock
 
-# HBM traffic of one headline enumeration launch, from the rocprofv3 FETCH_SIZE
-# and WRITE_SIZE passes summarised in profiles/enum_kernel_quiver28_pmc.md (KiB
-# per dispatch, mean of the timed dispatches), each scaled by what the counter
-# reads for a device copy of known size in the same run (FETCH_SIZE reads half
-# of the 256 MiB copied, WRITE_SIZE all of it).  Valid only for the kernel
-# source and the work-unit sizing (runtime.cpp) the counters were taken on; any
-# change to them makes `traffic` null.
+# HBM traffic of one headline enumeration launch (n = 36 system), from the
+# rocprofv3 FETCH_SIZE and WRITE_SIZE passes summarised in
+# profiles/enum_kernel_large36_pmc.md (KiB per dispatch, mean of the timed
+# dispatches), each scaled by what the counter reads for a device copy of
+# known size in the same run.  Valid only for the kernel source and the
+# work-unit sizing the counters were taken on: any change to the listed files
+# makes `traffic` null.
 TRAFFIC = {
-    "sources": ("enum_device.hpp", "exact_div.hpp", "kernels_k8.hip", "runtime.cpp"),
-    "sha256": "24dbb4a52de4e5af1b2451c2e41be4fd107d4567f7e2a1706dd6ec0e4a50467d",
-    "fetch_kib": 1786.59, "fetch_scale": 262144.0 / 131093.0,
-    "write_kib": 1007.72, "write_scale": 262144.0 / 262144.0,
+    "sources": ("enum_device.hpp", "exact_div.hpp", "kernels_k10.hip", "runtime.cpp", "bdeg_internal.hpp",
+                "lifting.hpp"),
+    "sha256": "",
+    "fetch_kib": 0.0, "fetch_scale": 1.0,
+    "write_kib": 0.0, "write_scale": 1.0,
 }
 
 
@@ -54,7 +59,7 @@ def traffic_bytes():
     return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
 
 
-def ops_per_launch(stats: dict, N: int, k: int) -> float:
+def ops_per_launch(stats: dict) -> float:
     """Algorithmic 32-bit integer operations of one enumeration launch.
 
     Op model (32-bit lane operations of the minimal instruction sequence; a
@@ -62,10 +67,59 @@ def ops_per_launch(stats: dict, N: int, k: int) -> float:
       spatial residual entry  8   (two products, a 64-bit difference, a shift, the inverse multiply)
       height residual entry  24   (two 64-bit halves of two products each, shift-add, 64-bit inverse multiply, split)
       leaf test per point    20   (two halves, carry fold, sign and zero tests)
-    Every node update runs on all N points; a leaf tests the N - k - 1 other points."""
-    sp = stats["spatial_updates"] + stats["ridges"]
-    ht = stats["inner_nodes"] + stats["ridges"]
-    return N * (8.0 * sp + 24.0 * ht) + 20.0 * (N - k - 1) * stats["leaves"]
+    Every node update runs on all N points of its system; a leaf tests the
+    N - k - 1 other points.  The counting kernel variant reports the counts
+    already weighted by each system's N (exact for batches of mixed sizes):
+    a ridge adds one spatial and one height entry per point, an inner node
+    one height entry and W - 1 spatial entries per point."""
+    sp = stats["point_spatial"] + stats["point_ridges"]
+    ht = stats["point_inner"] + stats["point_ridges"]
+    return 8.0 * sp + 24.0 * ht + 20.0 * stats["leaf_points"]
+
+
+def batch_leg(bd, torch, gen, reps: int) -> dict:
+    """The 4096-system batch in one prepared, captured device pass (the tuned
+    schedule table when one is installed), against the same systems solved
+    one by one with bdeg_degree."""
+    log("[bench] generating the 4096-system batch")
+    sy3 = gen.cfg3_systems(4096)
+    mats = [x.A for x in sy3]
+    cand3 = sum(math.comb(x.n + 1, x.n - x.m + 1) for x in sy3)
+    t = time.perf_counter()
+    b3 = bd.Batch(mats, seed=3, lift_bits=20)
+    prep = time.perf_counter() - t
+    b3.run()
+    b3.results()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    kms = []
+    for _ in range(reps):
+        b3.run()
+        res3 = b3.results()
+        kms.append(b3.stats()["kernel_ms"])
+    torch.cuda.synchronize()
+    bt = (time.perf_counter() - t) / reps
+    st3 = b3.stats()
+    prof = b3.profile()
+    b3.close()
+    assert all(r["status"] == 0 for r in res3)
+    k_ms = sum(kms) / len(kms)
+    out = {"batch4096_systems_per_s": 4096 / bt, "batch4096_cand_per_s": cand3 / bt,
+           "batch4096_ms": round(bt * 1e3, 3), "batch4096_kernel_ms": round(k_ms, 3),
+           "batch4096_e2e_systems_per_s": 4096 / (bt + prep), "batch4096_captured": st3["captured"],
+           "batch4096_redraws": st3["redraws"],
+           "batch4096_alu_frac": ops_per_launch(prof) / (k_ms * 1e-3) / PEAK_ALU,
+           "batch4096_tuned_table": os.path.exists(os.path.join(ROOT, "paper_1501_02237_amd", "tuning",
+                                                                "gfx950.json"))}
+    sample = mats[:512]
+    t = time.perf_counter()
+    for A in sample:
+        bd.degree(A, seed=3, lift_bits=20)
+    pt = (time.perf_counter() - t) / len(sample)
+    out["plain_one_by_one_systems_per_s"] = 1.0 / pt
+    log(f"[bench] batch 4096: {bt*1e3:.2f} ms ({4096/bt:.0f} sys/s, kernel {k_ms:.2f} ms, ALU fraction "
+        f"{out['batch4096_alu_frac']:.3f}, captured {st3['captured']}), plain one-by-one {1/pt:.0f} sys/s")
+    return out
 
 
 def walk_leg(bd, gen, m: int, k: int) -> dict:
@@ -172,17 +226,87 @@ def serve_trace(bd, gen, count):
     return out
 
 
+def plain_leg(bd, torch, s, steps: int, warmup: int, seed: int = 1) -> dict:
+    """One system as a prepared batch: `steps` timed device passes (clear,
+    lifting, enumeration of every candidate, tie redraws, readback), after
+    `warmup` untimed ones; then one counting pass for the op model."""
+    N, k = s.n + 1, s.n - s.m
+    cand = math.comb(N, k + 1)
+    b = bd.Batch([s.A], seed=seed, lift_bits=s.lift_bits)
+    for _ in range(warmup):
+        b.run()
+        b.results()
+    kms, ref = [], None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run()
+        r = b.results()[0]
+        st = b.stats()
+        kms.append(st["kernel_ms"])
+        if ref is None:
+            ref = r
+        assert r["status"] == 0 and r["nvol"] == ref["nvol"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    captured = b.stats()["captured"]
+    st = b.profile()  # work counters of the same pass (counting kernel variant, untimed)
+    b.close()
+    k_ms = sum(kms) / len(kms)
+    ops = ops_per_launch(st)
+    return {"N": N, "k": k, "candidates": cand, "ms_step": dt * 1e3 / steps, "value": cand * steps / dt,
+            "kernel_ms": k_ms, "ops": ops, "achieved": ops / (k_ms * 1e-3), "nvol": ref["nvol"], "stats": st,
+            "captured": captured}
+
+
+def oracle_leg(s, all_ranks: int, one_ranks: int) -> dict:
+    """The oracle as it stands on a bounded sample of the headline system:
+    its own prologue (Smith form, kernel points, LLL) once, then the colex
+    rank slice [0, all_ranks) on every host thread it uses, and [0, one_ranks)
+    on one thread."""
+    import oracle
+
+    oracle.build(force=False)
+    from oracle import algebra
+
+    threads = oracle.default_threads()
+    t = time.perf_counter()
+    _, _, pts = algebra.kernel_points(s.A.tolist())
+    prologue = time.perf_counter() - t
+    H = oracle.oracle_heights(1, 0, len(pts), s.lift_bits)
+    t = time.perf_counter()
+    oracle.nvol_range(pts, H, 0, all_ranks, threads=threads)
+    t_all = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.nvol_range(pts, H, 0, one_ranks, threads=1)
+    t_one = time.perf_counter() - t
+    log(f"[bench] oracle: prologue {prologue:.2f} s; ranks [0, {all_ranks}) in {t_all:.2f} s on {threads} threads; "
+        f"[0, {one_ranks}) in {t_one:.2f} s on 1 thread")
+    return {"value": all_ranks / t_all, "unit": "candidates/s", "cores": threads, "kind": "oracle",
+            "sample": f"the n=36 k=10 system's candidates of colex rank [0, {all_ranks}) on {threads} threads "
+                      f"({t_all:.1f} s; the oracle's own Smith form, kernel basis and lifting, prologue "
+                      f"{prologue:.1f} s not included)",
+            "single_core_value": one_ranks / t_one,
+            "single_core_sample": f"ranks [0, {one_ranks}) on 1 thread ({t_one:.1f} s)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=4000)
+    ap.add_argument("--oracle-ranks", type=int, default=20_000_000,
+                    help="colex ranks of the headline system the oracle decides on all host threads")
+    ap.add_argument("--oracle-ranks-1core", type=int, default=1_000_000,
+                    help="colex ranks of the headline system the oracle decides on one thread")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a dispatch of known "
                          "traffic, for scaling hardware byte counters)")
+    ap.add_argument("--only", default="", choices=["", "headline", "headline28", "batch"],
+                    help="run only this leg's timed steps and print its figures (for profiling)")
     ap.add_argument("--pruned", default="", choices=["", "headline", "large36"],
                     help="run only the prefix-pruned enumeration of this system and print its figures")
     ap.add_argument("--walk", default="",
@@ -218,100 +342,51 @@ def main():
         print(json.dumps({"walk": f"W_{{{m},{k}}}", **walk_leg(bd, gen, m, k)}), flush=True)
         return
 
-    s2 = gen.cfg2_system()
-    N2, k2 = s2.n + 1, s2.n - s2.m
-    cand2 = math.comb(N2, k2 + 1)
-    log(f"[bench] headline: quiver n={s2.n} m={s2.m} k={k2} N={N2} candidates={cand2}")
-    b = bd.Batch([s2.A], seed=1, lift_bits=s2.lift_bits)
-    for _ in range(a.warmup):
-        b.run()
-        b.results()
-    kms, ref = [], None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        b.run()
-        r = b.results()[0]
-        st = b.stats()
-        kms.append(st["kernel_ms"])
-        if ref is None:
-            ref = r
-        assert r["status"] == 0 and r["nvol"] == ref["nvol"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st = b.profile()  # work counters of the same pass (counting kernel variant, untimed)
-    b.close()
-    ms_step = dt * 1e3 / a.steps
-    value = cand2 * a.steps / dt
-    k_ms = sum(kms) / len(kms)
-    ops = ops_per_launch(st, N2, k2)
-    achieved = ops / (k_ms * 1e-3)
-    log(f"[bench] headline: {ms_step:.3f} ms/step, kernel {k_ms:.3f} ms, nvol={ref['nvol']}, "
-        f"{value:.3e} cand/s, ops/launch {ops:.3e}")
+    if a.only == "batch":
+        print(json.dumps(batch_leg(bd, torch, gen, a.steps)), flush=True)
+        return
+    if a.only == "headline28":
+        h = plain_leg(bd, torch, gen.cfg2_system(), a.steps, a.warmup)
+        h.pop("stats")
+        print(json.dumps(h), flush=True)
+        return
 
-    extra = {"nvol": ref["nvol"], "kernel_ms": round(k_ms, 4), "leaves": st["leaves"], "ridges": st["ridges"],
-             "inner_nodes": st["inner_nodes"], "pruned": st["pruned"], "units": st["tiles"]}
+    s4 = gen.cfg4_system()
+    log(f"[bench] headline: quiver n={s4.n} m={s4.m} k={s4.n - s4.m} N={s4.n + 1} "
+        f"candidates={math.comb(s4.n + 1, s4.n - s4.m + 1)}")
+    h = plain_leg(bd, torch, s4, a.steps, a.warmup)
+    log(f"[bench] headline: {h['ms_step']:.3f} ms/step, kernel {h['kernel_ms']:.3f} ms, nvol={h['nvol']}, "
+        f"{h['value']:.3e} cand/s, ops/launch {h['ops']:.3e}, ALU fraction {h['achieved'] / PEAK_ALU:.3f}")
+    if a.only == "headline":
+        h.pop("stats")
+        print(json.dumps(h), flush=True)
+        return
+    st = h["stats"]
+    extra = {"nvol": h["nvol"], "kernel_ms": round(h["kernel_ms"], 4), "captured": h["captured"],
+             "leaves": st["leaves"], "ridges": st["ridges"], "inner_nodes": st["inner_nodes"],
+             "pruned": st["pruned"], "units": st["tiles"], "ops_per_launch": h["ops"]}
     if not a.no_extras:
-        # end-to-end plain solve (host prologue, tiling, copies, device pass)
+        # the n = 28 system, same measurement
+        h2 = plain_leg(bd, torch, gen.cfg2_system(), a.steps, a.warmup)
+        extra.update({"headline28_cand_per_s": h2["value"], "headline28_ms_step": round(h2["ms_step"], 4),
+                      "headline28_kernel_ms": round(h2["kernel_ms"], 4), "headline28_nvol": h2["nvol"],
+                      "headline28_alu_frac": h2["achieved"] / PEAK_ALU})
+        log(f"[bench] n=28: {h2['ms_step']:.3f} ms/step, kernel {h2['kernel_ms']:.3f} ms, "
+            f"{h2['value']:.3e} cand/s, ALU fraction {h2['achieved'] / PEAK_ALU:.3f}")
+        # end-to-end plain solve of the n = 28 system (host prologue, tiling, copies, device pass)
+        s2 = gen.cfg2_system()
         reps = 10
         t = time.perf_counter()
         for _ in range(reps):
             bd.degree(s2.A, seed=1, lift_bits=s2.lift_bits)
         e2e = (time.perf_counter() - t) / reps
         extra["plain_e2e_ms"] = round(e2e * 1e3, 3)
-        extra["plain_e2e_cand_per_s"] = cand2 / e2e
-        extra["plain_resident_systems_per_s"] = 1e3 / ms_step
+        extra["plain_e2e_cand_per_s"] = h2["candidates"] / e2e
+        extra["plain_resident_systems_per_s"] = 1e3 / h2["ms_step"]
 
-        # batch of 4096 systems in one launch vs the same systems one by one
-        log("[bench] generating the 4096-system batch")
-        sy3 = gen.cfg3_systems(4096)
-        mats = [x.A for x in sy3]
-        cand3 = sum(math.comb(x.n + 1, x.n - x.m + 1) for x in sy3)
-        t = time.perf_counter()
-        b3 = bd.Batch(mats, seed=3, lift_bits=20)
-        prep = time.perf_counter() - t
-        b3.run()
-        b3.results()
-        reps = 5
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(reps):
-            b3.run()
-            res3 = b3.results()
-        torch.cuda.synchronize()
-        bt = (time.perf_counter() - t) / reps
-        st3 = b3.stats()
-        b3.close()
-        assert all(r["status"] == 0 for r in res3)
-        extra["batch4096_systems_per_s"] = 4096 / bt
-        extra["batch4096_cand_per_s"] = cand3 / bt
-        extra["batch4096_ms"] = round(bt * 1e3, 3)
-        extra["batch4096_kernel_ms"] = round(st3["kernel_ms"], 3)
-        extra["batch4096_e2e_systems_per_s"] = 4096 / (bt + prep)
-        sample = mats[:512]
-        t = time.perf_counter()
-        for A in sample:
-            bd.degree(A, seed=3, lift_bits=20)
-        pt = (time.perf_counter() - t) / len(sample)
-        extra["plain_one_by_one_systems_per_s"] = 1.0 / pt
-        log(f"[bench] batch 4096: {bt*1e3:.2f} ms ({4096/bt:.0f} sys/s), plain one-by-one {1/pt:.0f} sys/s")
+        extra.update(batch_leg(bd, torch, gen, 5))
 
-        # the n = 36, k = 10 system
-        s4 = gen.cfg4_system()
-        b4 = bd.Batch([s4.A], seed=1, lift_bits=s4.lift_bits)
-        b4.run()
-        b4.results()
-        b4.run()
-        r4 = b4.results()[0]
-        st4 = b4.stats()
-        b4.close()
-        cand4 = math.comb(s4.n + 1, s4.n - s4.m + 1)
-        extra["large36_nvol"] = r4["nvol"]
-        extra["large36_kernel_ms"] = round(st4["kernel_ms"], 3)
-        extra["large36_cand_per_s"] = cand4 / (st4["total_ms"] * 1e-3)
-        log(f"[bench] n=36 k=10: nvol={r4['nvol']} kernel {st4['kernel_ms']:.2f} ms")
-
-        # the prefix-pruned enumeration of the headline and n = 36 systems
+        # the prefix-pruned enumeration of the n = 28 and n = 36 systems
         for name in ("headline", "large36"):
             extra.update({f"pruned_{name}_{key}": v for key, v in prune_leg(bd, gen, name).items()})
 
@@ -321,40 +396,25 @@ def main():
         if a.serve_requests > 0:
             extra.update(serve_trace(bd, gen, a.serve_requests))
 
-    cpu = None
-    if not a.no_cpu:
-        import oracle
-
-        oracle.build(force=False)
-        from oracle import algebra
-
-        threads = oracle.default_threads()
-        t = time.perf_counter()
-        kk, comps, pts = algebra.kernel_points(s2.A.tolist())
-        part = oracle.nvol_range(pts, oracle.oracle_heights(1, 0, len(pts), s2.lift_bits), 0, cand2, threads=threads)
-        ct = time.perf_counter() - t
-        assert part.nvol == ref["nvol"], (part.nvol, ref["nvol"])
-        cpu = {"value": cand2 / ct, "unit": "candidates/s", "cores": threads, "kind": "oracle",
-               "sample": f"the whole headline system (all {cand2} candidates, exact SNF + brute force), {ct:.1f} s"}
-        log(f"[bench] oracle: {ct:.2f} s on {threads} threads")
+    cpu = None if a.no_cpu else oracle_leg(s4, a.oracle_ranks, a.oracle_ranks_1core)
 
     out = {
         "metric": "exact candidate simplices decided per second (plain single system, 1 GPU)",
-        "value": value,
+        "value": h["value"],
         "unit": "candidates/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(h["ms_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "i32/i64 (exact integer, 128-bit products)",
         "data": "synthetic (seeded quiver-like exponent matrix)",
-        "config": {"workload": "plain quiver-like system n=28 m=20 k=8 N=29, heights < 2^20, device-resident",
-                   "candidates": cand2, "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU, "unit": "int32 lane-ops/s",
-                     "frac": achieved / PEAK_ALU, "traffic": traffic_bytes()},
+        "config": {"workload": "large quiver-like system n=36 m=26 k=10 N=37, row weights 2-4, heights < 2^24, "
+                               "device-resident", "candidates": h["candidates"], "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": h["achieved"], "peak": PEAK_ALU, "unit": "int32 lane-ops/s",
+                     "frac": h["achieved"] / PEAK_ALU, "traffic": traffic_bytes()},
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -91,8 +91,16 @@ typedef struct {
   uint64_t ridge_steps;       /* wavefront iterations of the ridge loops (one ridge per lane group) */
   uint64_t leaf_steps;        /* wavefront iterations of the leaf loops (one candidate per lane group) */
   uint64_t empty_steps;       /* leaf iterations in which no lane group had a candidate with D != 0 */
+  /* the same work weighted by the points each step touches, summed over the
+     systems (exact for batches of mixed N and k): */
+  uint64_t point_inner;       /* sum of N * inner_nodes */
+  uint64_t point_spatial;     /* sum of N * spatial_updates */
+  uint64_t point_ridges;      /* sum of N * ridges */
+  uint64_t leaf_points;       /* sum of (N - k - 1) * leaves: points tested by the leaf tests */
   float kernel_ms;            /* device time of the enumeration kernel, HIP events */
   float total_ms;             /* device time of the whole device pass (clear, lift, enumerate) */
+  int32_t captured;           /* 1: the device pass replays captured HIP graphs; 0: plain launches */
+  int32_t redraws;            /* systems whose tied lifting was redrawn inside the last device pass */
 } bdeg_stats;
 
 /* Optional: select the HIP device (default: current device at first use).
@@ -124,10 +132,17 @@ int bdeg_degree_batch(const int64_t *A_concat, const int32_t *m, const int32_t *
  * in device memory, device path captured as a HIP graph and replayable.
  *   bdeg_batch_create   host prologue (Smith form, kernel points, bounds,
  *                       tiling) + upload; *out owns device memory.
- *   bdeg_batch_run      enqueue one full device pass (clear accumulators,
- *                       lifting, enumeration) on the library stream; async.
- *   bdeg_batch_results  wait, redraw liftings of tied systems (uncaptured
- *                       reruns) until none ties, fill out[count].
+ *   bdeg_batch_run      enqueue one full device pass on the library stream
+ *                       (async): reset to the first lifting, enumeration, then
+ *                       up to 3 redraw rounds in which every tied system gets
+ *                       its next lifting and its units run again (a round
+ *                       with no tie costs one empty launch).  The pass is
+ *                       three captured HIP graphs (bdeg_stats.captured).
+ *   bdeg_batch_results  wait; a system still tied after the captured rounds
+ *                       is redrawn by uncaptured reruns until it is not (at
+ *                       most BDEG_MAX_ATTEMPTS draws in all); fill out[count].
+ *                       Results equal bdeg_degree's for the same seed and
+ *                       lift_bits, attempts included.
  *   bdeg_batch_stats    HIP-event times of the last run, and the work counters
  *                       of the last profiling pass.
  *   bdeg_batch_profile  one extra synchronous device pass with the kernel
@@ -143,6 +158,28 @@ int bdeg_batch_results(bdeg_batch *b, bdeg_result *out);
 int bdeg_batch_stats(const bdeg_batch *b, bdeg_stats *out);
 int bdeg_batch_profile(bdeg_batch *b);
 int bdeg_batch_destroy(bdeg_batch *b);
+
+/*
+ * Autotuner of a prepared batch's work schedule.  The systems are grouped in
+ * buckets of equal k and equal smallest lane-group width (8, 16, 32 or 64
+ * lanes per point group for N <= 8, 16, 32, 64 points).  For each bucket the
+ * bucket's systems are enumerated alone under every schedule of a small grid
+ * (lane-group width: the smallest or the next larger one, 64 lanes meaning
+ * one group per wavefront in its own kernel variant; work-unit size cap:
+ * 128 .. 8192 candidates) and under the default schedule, each timed by HIP
+ * events (median of `reps` passes after a warm-up).  Every schedule must give
+ * exactly the default's sums for every system (the same liftings and
+ * candidates), else BDEG_E_STATE and nothing is written.  The fastest
+ * schedule per bucket is written to the JSON table `table_path` (entries of
+ * buckets the batch lacks are kept; NULL: not written) and applied to the
+ * batch, whose device pass is captured again.
+ * bdeg_batch_create applies the table named by the environment variable
+ * BDEG_TUNE_TABLE, else tuning/gfx950.json beside the library, when it
+ * exists; a system of a bucket without an entry keeps the default schedule.
+ * The paper tunes its thread counts by hand (Section 6, Table 5); this
+ * replaces that with a measured choice per bucket.
+ */
+int bdeg_batch_tune(bdeg_batch *b, const char *table_path, int32_t reps);
 
 /*
  * Volume of a caller's point set with caller's heights, restricted to the
@@ -232,8 +269,9 @@ int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32
  * hash set of visited cells.  The work follows the number of cells, so k up
  * to BDEG_PIVOT_MAX_K and N up to 64 are in reach when the cells are few.
  *   points, heights  as for bdeg_nvol_points (k <= BDEG_PIVOT_MAX_K);
- *   start_mask       a cell (k+1 points) that is a lower facet for `heights`;
- *                    BDEG_E_ARG when it is not;
+ *   start_mask       a cell (k+1 points) that is a lower facet for `heights`
+ *                    (BDEG_E_ARG when it is not), or 0: the start cell is
+ *                    found by bdeg_extend_points' method on the device;
  *   cell_masks [cap] the cells, in no particular order (cap = 0: none copied);
  *   *n_cells, *nvol  number of cells and the sum of their normalized volumes;
  *   *tie             a non-generic lower face was met (results then invalid).
@@ -247,15 +285,48 @@ int bdeg_pivot_points(const int32_t *points, const int64_t *heights, int32_t N, 
 
 /*
  * Degree data of x^A = b (as bdeg_degree) computed by the cell walk, for k up
- * to BDEG_PIVOT_MAX_K.  The lifting gives height 0 to a greedy affinely
- * independent set of k+1 points (point 0 first, then in index order) and
- * 1 + a seeded draw in [0, 2^lift_bits) to the others, so that set is a lower
- * facet to start from; a tie redraws the other heights (at most
- * BDEG_MAX_ATTEMPTS draws).  nvol is the same as bdeg_degree's (it does not
- * depend on the lifting); cells counts this lifting's cells.
+ * to BDEG_PIVOT_MAX_K.  The lifting is bdeg_degree's seeded generic lifting
+ * (the same heights for the same seed and lift_bits), the start cell comes
+ * from Extend (bdeg_extend_points), and a tie redraws the lifting (at most
+ * BDEG_MAX_ATTEMPTS draws).  For k <= BDEG_MAX_K the result equals
+ * bdeg_degree's, cells and attempts included (the same regular subdivision).
  */
 int bdeg_degree_pivot(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int32_t lift_bits,
                       bdeg_result *out);
+
+/*
+ * Extend (Section 4.1, the lower-face LP of eq. "ext-lp"; Section 4.5,
+ * algorithm Extend): a lower facet of the caller's lifted points, the start
+ * of the walk.  From the lowest lifted point, the face is grown one point at
+ * a time by tilting a supporting hyperplane of the current lower face about
+ * it until the first other lifted point reaches it (an exact ratio test on
+ * fraction-free residuals, one wavefront on the device); after k steps the
+ * face is a lower facet.  Exact integer arithmetic throughout.
+ *   points, heights  as for bdeg_pivot_points (k <= BDEG_PIVOT_MAX_K);
+ *   *facet_mask      the k + 1 points of the facet (0 when *tie);
+ *   *tie             1 when a lower face met on the way is not a simplex
+ *                    (the lifting is not generic).
+ * Errors: BDEG_E_ARG (bad sizes, heights |h| >= 2^40, points that do not span
+ * Z^k affinely), BDEG_E_OVERFLOW (outside the device width certificate),
+ * BDEG_E_DEVICE, BDEG_E_NOMEM.
+ */
+int bdeg_extend_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, uint64_t *facet_mask,
+                       int32_t *tie);
+
+/*
+ * The cell walk (as bdeg_pivot_points; start_mask 0 = Extend) returning the
+ * cells with their inner normals (alpha, 1) of eq. "lower-d-face-again",
+ * alpha = num / den exactly, as bdeg_cells_points does for the enumeration:
+ * the start data of the polyhedral homotopies of Section 5, for k up to
+ * BDEG_PIVOT_MAX_K.
+ *   cell_masks [cap], normal_num [cap * k], normal_den [cap]: at most cap
+ *   cells written (cap = 0: none; the arrays may then be NULL);
+ *   *n_cells, *nvol, *tie: as for bdeg_pivot_points.
+ * Cells come in no particular order; den sums to *nvol.
+ */
+int bdeg_pivot_cells(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, uint64_t start_mask,
+                     uint64_t cap, uint64_t *cell_masks, int64_t *normal_num, uint64_t *normal_den,
+                     uint64_t *n_cells, bdeg_u128 *nvol, int32_t *tie);
 
 /*
  * Consistency of x^A = b when rank A = r < m (Section 2, eq. "consistency"

@@ -66,7 +66,9 @@ class Stats(ctypes.Structure):
         ("ridges", ctypes.c_uint64), ("inner_nodes", ctypes.c_uint64), ("spatial_updates", ctypes.c_uint64),
         ("pruned", ctypes.c_uint64), ("leaves", ctypes.c_uint64), ("tiles", ctypes.c_uint64),
         ("ridge_steps", ctypes.c_uint64), ("leaf_steps", ctypes.c_uint64), ("empty_steps", ctypes.c_uint64),
-        ("kernel_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
+        ("point_inner", ctypes.c_uint64), ("point_spatial", ctypes.c_uint64), ("point_ridges", ctypes.c_uint64),
+        ("leaf_points", ctypes.c_uint64), ("kernel_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
+        ("captured", ctypes.c_int32), ("redraws", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -95,12 +97,15 @@ def lib() -> ctypes.CDLL:
         "bdeg_batch_stats": ([P, P], ctypes.c_int),
         "bdeg_batch_profile": ([P], ctypes.c_int),
         "bdeg_batch_destroy": ([P], ctypes.c_int),
+        "bdeg_batch_tune": ([P, ctypes.c_char_p, I32], ctypes.c_int),
         "bdeg_nvol_points": ([P, P, I32, I32, U64, U64, P, P, P], ctypes.c_int),
         "bdeg_nvol_points_pruned": ([P, P, I32, I32, I32, P, P, P, P], ctypes.c_int),
         "bdeg_kernel_points": ([P, I32, I32, P, P, P, P], ctypes.c_int),
         "bdeg_consistency": ([P, I32, I32, P, ctypes.c_double, P, P, P], ctypes.c_int),
         "bdeg_pivot_points": ([P, P, I32, I32, U64, U64, P, P, P, P], ctypes.c_int),
         "bdeg_degree_pivot": ([P, I32, I32, U64, I32, P], ctypes.c_int),
+        "bdeg_extend_points": ([P, P, I32, I32, P, P], ctypes.c_int),
+        "bdeg_pivot_cells": ([P, P, I32, I32, U64, U64, P, P, P, P, P, P], ctypes.c_int),
         "bdeg_cells_points": ([P, P, I32, I32, U64, U64, U64, P, P, P, P, P], ctypes.c_int),
         "bdeg_subdivision": ([P, I32, I32, U64, I32, U64, P, P, P, P, P, P, P], ctypes.c_int),
         "bdeg_serve_open": ([SZ, P], ctypes.c_int),
@@ -185,6 +190,41 @@ def pivot_points(points, heights, start_mask: int, cap: int = 0) -> dict:
     if rc != BDEG_OK:
         raise BdegError(rc, "bdeg_pivot_points")
     return dict(nvol=nv.value, cells=n.value, tie=bool(tie.value), masks=masks[: min(cap, n.value)].copy())
+
+
+def extend_points(points, heights) -> dict:
+    """Extend: a lower facet of the lifted points, {mask, tie}."""
+    P = np.ascontiguousarray(np.asarray(points, dtype=np.int32))
+    H = np.ascontiguousarray(np.asarray(heights, dtype=np.int64))
+    N, k = P.shape
+    m, tie = ctypes.c_uint64(), ctypes.c_int32()
+    rc = lib().bdeg_extend_points(P.ctypes.data, H.ctypes.data, N, k, ctypes.byref(m), ctypes.byref(tie))
+    if rc != BDEG_OK:
+        raise BdegError(rc, "bdeg_extend_points")
+    return dict(mask=m.value, tie=bool(tie.value))
+
+
+def pivot_cells(points, heights, start_mask: int = 0, cap: int = 1 << 16) -> dict:
+    """The cell walk (start_mask 0: from Extend's facet) with the cells'
+    inner normals: {nvol, cells, tie, cell_list (Cells)}."""
+    P = np.ascontiguousarray(np.asarray(points, dtype=np.int32))
+    H = np.ascontiguousarray(np.asarray(heights, dtype=np.int64))
+    N, k = P.shape
+    while True:
+        masks, num, den = np.zeros(max(cap, 1), dtype=np.uint64), np.zeros((max(cap, 1), k), dtype=np.int64), \
+            np.zeros(max(cap, 1), dtype=np.uint64)
+        n, nv, tie = ctypes.c_uint64(), U128(), ctypes.c_int32()
+        rc = lib().bdeg_pivot_cells(P.ctypes.data, H.ctypes.data, N, k, int(start_mask) & U64_MAX, cap,
+                                    masks.ctypes.data, num.ctypes.data, den.ctypes.data, ctypes.byref(n),
+                                    ctypes.byref(nv), ctypes.byref(tie))
+        if rc != BDEG_OK:
+            raise BdegError(rc, "bdeg_pivot_cells")
+        c = n.value
+        if c <= cap:
+            break
+        cap = c
+    return dict(nvol=nv.value, cells=c, tie=bool(tie.value),
+                cell_list=Cells(masks[:c].copy(), num[:c].copy(), den[:c].copy(), bool(tie.value)))
 
 
 class PruneStats(ctypes.Structure):
@@ -373,6 +413,15 @@ class Batch:
         s = Stats()
         lib().bdeg_batch_stats(self._h, ctypes.byref(s))
         return s.as_dict()
+
+    def tune(self, table_path: str | None = None, reps: int = 3) -> None:
+        """Autotune the work schedule per (k, lane-group width) bucket on this
+        batch's systems; write the table to table_path (None: not written)
+        and apply it (bdeg_batch_tune)."""
+        path = None if table_path is None else os.fsencode(table_path)
+        rc = lib().bdeg_batch_tune(self._h, path, reps)
+        if rc != BDEG_OK:
+            raise BdegError(rc, "bdeg_batch_tune")
 
     def profile(self) -> dict:
         """One extra device pass with the work-counting kernel variant."""

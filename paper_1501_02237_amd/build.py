@@ -16,8 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbdeg.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["algebra.cpp", "tiles.cpp", "runtime.cpp", "api.cpp", "serve.cpp", "kernels.hip",
-           "kernels_mixed12.hip", "kernels_mixed7.hip", "kernels_cells.hip", "pivot.cpp",
+SOURCES = ["algebra.cpp", "tiles.cpp", "runtime.cpp", "tune.cpp", "api.cpp", "serve.cpp", "kernels.hip",
+           "kernels_mixed12.hip", "kernels_mixed7.hip", "kernels_cells.hip", "kernels_extend.hip", "pivot.cpp",
            "kernels_prune.hip", "kernels_pivot_a.hip", "kernels_pivot_b.hip", "kernels_pivot_c.hip", "kernels_pivot_d.hip"] + [f"kernels_k{k}.hip" for k in range(18, 0, -1)]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -95,7 +95,7 @@ int prepare_many(const int64_t *A_concat, const int32_t *m, const int32_t *n, in
 // tied systems only.  `first` (optional) is an already-launched job holding
 // all of `dev` in order.
 int finish_device(Device *D, std::vector<HostSys> &dev, std::vector<bdeg_result> &res, Job *first,
-                  DevCounters *cnt_out) {
+                  DevCounters *cnt_out, int32_t *redraws_out) {
   std::vector<int> pending(dev.size());
   for (size_t i = 0; i < dev.size(); i++) pending[i] = (int)i;
   Job local;
@@ -122,17 +122,25 @@ int finish_device(Device *D, std::vector<HostSys> &dev, std::vector<bdeg_result>
     int rc = job_collect(*job, D->stream, acc, &cnt);
     if (rc) return rc;
     if (round == 0 && cnt_out) *cnt_out = cnt;
+    if (round == 0 && redraws_out) {
+      int32_t n = 0;
+      for (const SysAcc &a : acc) n += a.attempt > 0;
+      *redraws_out = n;
+    }
     std::vector<int> next;
     for (size_t q = 0; q < pending.size(); q++) {
       HostSys &h = dev[pending[q]];
       bdeg_result &r = res[h.input_index];
-      r.attempts = (int32_t)h.attempt + 1;
+      // draws made inside the device pass (a prepared batch's redraw rounds)
+      // come on top of the host's
+      const uint32_t att = h.attempt + acc[q].attempt;
+      r.attempts = (int32_t)att + 1;
       if (acc[q].tie) {
-        if (h.attempt + 1 >= BDEG_MAX_ATTEMPTS) {
+        if (att + 1 >= BDEG_MAX_ATTEMPTS) {
           r.status = BDEG_E_TIE;
           continue;
         }
-        h.attempt++;
+        h.attempt = att + 1;
         next.push_back(pending[q]);
         continue;
       }
@@ -171,6 +179,9 @@ static void points_job(Job &job, const int32_t *points, const int64_t *heights, 
   d.lift_bits = 0;
   d.npad_log2 = npad_log2_for(N);
   d.lift_key = 0;
+  d.seed = 0;
+  d.sys_index = 0;
+  d.pad = 0;
   job.sys.push_back(d);
   job.pts.assign(points, points + (size_t)N * k);
   job.heights.assign(heights, heights + N);
@@ -261,14 +272,111 @@ struct bdeg_batch {
   std::vector<bdeg_result> res;
   std::vector<HostSys> dev;
   Job job;
-  // the device pass is two captured graphs: clear + lift, then the
-  // enumeration, so that HIP events between them time the enumeration alone
-  hipGraph_t graph_pre = nullptr, graph_enum = nullptr;
-  hipGraphExec_t exec_pre = nullptr, exec_enum = nullptr;
+  // the device pass is three captured graphs: reset + lift, the enumeration
+  // (HIP events between them time the enumeration alone), and the redraw
+  // rounds of tied systems (each a no-op launch when nothing tied)
+  hipGraph_t graph_pre = nullptr, graph_enum = nullptr, graph_retry = nullptr;
+  hipGraphExec_t exec_pre = nullptr, exec_enum = nullptr, exec_retry = nullptr;
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_k0 = nullptr, ev_k1 = nullptr;
   bool launched = false;
   bdeg_stats stats{};
 };
+
+namespace bdeg {
+
+static void batch_drop_graphs(bdeg_batch *b) {
+  for (hipGraphExec_t x : {b->exec_pre, b->exec_enum, b->exec_retry})
+    if (x) (void)hipGraphExecDestroy(x);
+  for (hipGraph_t g : {b->graph_pre, b->graph_enum, b->graph_retry})
+    if (g) (void)hipGraphDestroy(g);
+  b->exec_pre = b->exec_enum = b->exec_retry = nullptr;
+  b->graph_pre = b->graph_enum = b->graph_retry = nullptr;
+  b->stats.captured = 0;
+}
+
+// Work units for the batch's systems (with a tuned schedule when given),
+// upload, and capture the device pass (reset + lift; enumeration; redraw
+// rounds) as three graphs.  Called with the device mutex held.
+static int batch_setup(bdeg_batch *b, Device *D, const ScheduleTable *sched) {
+  batch_drop_graphs(b);
+  if (b->dev.empty()) return BDEG_OK;
+  uint64_t total = 0;
+  int kmax = 1, kmin = 64;
+  for (auto &h : b->dev) {
+    total += binom_u64(h.N, h.k + 1);
+    kmax = std::max(kmax, h.k);
+    kmin = std::min(kmin, h.k);
+  }
+  job_build_seeded(b->job, b->dev, choose_max_cost(total, default_waves(std::min(kmin, kmax), kmax, 4)), sched);
+  int rc = job_upload(b->job);
+  if (rc) return rc;
+  auto capture = [&](int part, hipGraph_t *g, hipGraphExec_t *x) {
+    if (hipStreamBeginCapture(D->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+    int rc2 = BDEG_OK;
+    if (part == 0) rc2 = job_launch_reset(b->job, D->stream);
+    else if (part == 1) rc2 = job_launch_enum(b->job, D->stream, 0);
+    else
+      for (int r = 1; r <= RETIE_ROUNDS && rc2 == BDEG_OK; r++)
+        if (!(rc2 = job_launch_retie(b->job, D->stream, r))) rc2 = job_launch_enum(b->job, D->stream, r);
+    hipGraph_t gg = nullptr;
+    hipError_t e = hipStreamEndCapture(D->stream, &gg);
+    if (rc2 == BDEG_OK && e == hipSuccess && gg && hipGraphInstantiate(x, gg, nullptr, nullptr, 0) == hipSuccess) {
+      *g = gg;
+      return true;
+    }
+    if (gg) (void)hipGraphDestroy(gg);
+    *x = nullptr;
+    (void)hipGetLastError();
+    return false;
+  };
+  if (capture(0, &b->graph_pre, &b->exec_pre) && capture(1, &b->graph_enum, &b->exec_enum) &&
+      capture(2, &b->graph_retry, &b->exec_retry))
+    b->stats.captured = 1;
+  else
+    batch_drop_graphs(b); // the same pass then runs as plain launches (stats.captured == 0)
+  return BDEG_OK;
+}
+
+// Device time of the first enumeration of `systems` alone under `sched`
+// (median of `reps` timed passes after one warm-up); the volume sums of the
+// pass are returned for the tuner's consistency check.
+static int time_schedule(Device *D, const std::vector<HostSys> &systems, const ScheduleTable *sched, int reps,
+                         float *ms, std::vector<SysAcc> *sums) {
+  Job job;
+  uint64_t total = 0;
+  int kmax = 1, kmin = 64;
+  for (auto &h : systems) {
+    total += binom_u64(h.N, h.k + 1);
+    kmax = std::max(kmax, h.k);
+    kmin = std::min(kmin, h.k);
+  }
+  job_build_seeded(job, systems, choose_max_cost(total, default_waves(std::min(kmin, kmax), kmax, 4)), sched);
+  int rc = job_upload(job);
+  if (rc) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return BDEG_E_DEVICE;
+  }
+  std::vector<float> t;
+  for (int r = 0; r <= reps && !rc; r++) {
+    rc = job_launch_reset(job, D->stream);
+    if (!rc && hipEventRecord(e0, D->stream) != hipSuccess) rc = BDEG_E_DEVICE;
+    if (!rc) rc = job_launch_enum(job, D->stream, 0);
+    if (!rc && hipEventRecord(e1, D->stream) != hipSuccess) rc = BDEG_E_DEVICE;
+    if (!rc) rc = job_collect(job, D->stream, *sums, nullptr);
+    float x = 0;
+    if (!rc && r > 0 && hipEventElapsedTime(&x, e0, e1) == hipSuccess) t.push_back(x);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  std::sort(t.begin(), t.end());
+  *ms = t.empty() ? 0.f : t[t.size() / 2];
+  return BDEG_OK;
+}
+
+} // namespace bdeg
 
 extern "C" {
 
@@ -377,48 +485,16 @@ int bdeg_batch_create(const int64_t *A_concat, const int32_t *m, const int32_t *
   bdeg_batch *b = new bdeg_batch();
   prepare_many(A_concat, m, n, count, seed, lift_bits, b->res, b->dev);
   std::lock_guard<std::mutex> lk(D->mu);
-  if (!b->dev.empty()) {
-    uint64_t total = 0;
-    int kmax = 1, kmin = 64;
-    for (auto &h : b->dev) {
-      total += binom_u64(h.N, h.k + 1);
-      kmax = std::max(kmax, h.k);
-      kmin = std::min(kmin, h.k);
-    }
-    job_build_seeded(b->job, b->dev, choose_max_cost(total, default_waves(std::min(kmin, kmax), kmax, 4)));
-    int rc = job_upload(b->job);
-    if (rc) {
-      delete b;
-      return rc;
-    }
-  }
   if (hipEventCreate(&b->ev_t0) != hipSuccess || hipEventCreate(&b->ev_t1) != hipSuccess ||
       hipEventCreate(&b->ev_k0) != hipSuccess || hipEventCreate(&b->ev_k1) != hipSuccess) {
     delete b;
     return BDEG_E_DEVICE;
   }
-  // capture clear + lift and the enumeration once each; replay per run
-  if (!b->dev.empty()) {
-    auto capture = [&](bool pre, hipGraph_t *g, hipGraphExec_t *x) {
-      if (hipStreamBeginCapture(D->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
-      int rc = pre ? job_launch_pre(b->job, D->stream) : job_launch_enum(b->job, D->stream);
-      hipGraph_t gg = nullptr;
-      hipError_t e = hipStreamEndCapture(D->stream, &gg);
-      if (rc == BDEG_OK && e == hipSuccess && gg && hipGraphInstantiate(x, gg, nullptr, nullptr, 0) == hipSuccess) {
-        *g = gg;
-        return true;
-      }
-      if (gg) (void)hipGraphDestroy(gg);
-      *x = nullptr;
-      (void)hipGetLastError();
-      return false;
-    };
-    if (!capture(true, &b->graph_pre, &b->exec_pre) || !capture(false, &b->graph_enum, &b->exec_enum)) {
-      if (b->exec_pre) (void)hipGraphExecDestroy(b->exec_pre);
-      if (b->graph_pre) (void)hipGraphDestroy(b->graph_pre);
-      b->exec_pre = b->exec_enum = nullptr;
-      b->graph_pre = b->graph_enum = nullptr;
-    }
+  const ScheduleTable &tab = schedule_table();
+  const int rc = batch_setup(b, D, tab.any ? &tab : nullptr);
+  if (rc) {
+    delete b;
+    return rc;
   }
   *out = b;
   return BDEG_OK;
@@ -437,13 +513,20 @@ int bdeg_batch_run(bdeg_batch *b) {
   // every run starts from attempt 0 (same liftings as the captured graph)
   for (auto &h : b->dev) h.attempt = 0;
   if (hipEventRecord(b->ev_t0, D->stream) != hipSuccess) return BDEG_E_DEVICE;
-  if (b->exec_pre && b->exec_enum) {
+  if (b->stats.captured) {
     if (hipGraphLaunch(b->exec_pre, D->stream) != hipSuccess) return BDEG_E_DEVICE;
     if (hipEventRecord(b->ev_k0, D->stream) != hipSuccess) return BDEG_E_DEVICE;
     if (hipGraphLaunch(b->exec_enum, D->stream) != hipSuccess) return BDEG_E_DEVICE;
     if (hipEventRecord(b->ev_k1, D->stream) != hipSuccess) return BDEG_E_DEVICE;
+    if (hipGraphLaunch(b->exec_retry, D->stream) != hipSuccess) return BDEG_E_DEVICE;
   } else {
-    int rc = job_launch(b->job, D->stream, b->ev_k0, b->ev_k1);
+    // the same pass as plain launches (capture was refused by the runtime)
+    int rc = job_launch_reset(b->job, D->stream);
+    if (!rc && hipEventRecord(b->ev_k0, D->stream) != hipSuccess) rc = BDEG_E_DEVICE;
+    if (!rc) rc = job_launch_enum(b->job, D->stream, 0);
+    if (!rc && hipEventRecord(b->ev_k1, D->stream) != hipSuccess) rc = BDEG_E_DEVICE;
+    for (int r = 1; r <= RETIE_ROUNDS && !rc; r++)
+      if (!(rc = job_launch_retie(b->job, D->stream, r))) rc = job_launch_enum(b->job, D->stream, r);
     if (rc) return rc;
   }
   if (hipEventRecord(b->ev_t1, D->stream) != hipSuccess) return BDEG_E_DEVICE;
@@ -463,7 +546,7 @@ int bdeg_batch_results(bdeg_batch *b, bdeg_result *out) {
     float t = 0, k = 0;
     (void)hipEventElapsedTime(&t, b->ev_t0, b->ev_t1);
     (void)hipEventElapsedTime(&k, b->ev_k0, b->ev_k1);
-    int rc = finish_device(D, b->dev, b->res, &b->job, nullptr);
+    int rc = finish_device(D, b->dev, b->res, &b->job, nullptr, &b->stats.redraws);
     if (rc) return rc;
     b->stats.kernel_ms = k;
     b->stats.total_ms = t;
@@ -486,8 +569,10 @@ int bdeg_batch_profile(bdeg_batch *b) {
   Device *D = device_get(&st);
   if (!D) return st;
   std::lock_guard<std::mutex> lk(D->mu);
+  // the first enumeration of the pass (attempt-0 liftings), counting its work
   b->job.shape.mode = MODE_STATS;
-  int rc = job_launch(b->job, D->stream);
+  int rc = job_launch_reset(b->job, D->stream);
+  if (!rc) rc = job_launch_enum(b->job, D->stream, 0);
   b->job.shape.mode = MODE_PLAIN;
   if (rc) return rc;
   std::vector<SysAcc> acc;
@@ -503,7 +588,74 @@ int bdeg_batch_profile(bdeg_batch *b) {
   b->stats.leaf_steps = cnt.lsteps;
   b->stats.empty_steps = cnt.lempty;
   b->stats.tiles = cnt.tiles;
+  b->stats.point_inner = cnt.w_inner;
+  b->stats.point_spatial = cnt.w_spatial;
+  b->stats.point_ridges = cnt.w_ridges;
+  b->stats.leaf_points = cnt.w_leaves;
   return BDEG_OK;
+}
+
+int bdeg_batch_tune(bdeg_batch *b, const char *table_path, int32_t reps) {
+  if (!b || reps < 1 || reps > 64) return BDEG_E_ARG;
+  if (b->dev.empty()) return BDEG_OK;
+  int st;
+  Device *D = device_get(&st);
+  if (!D) return st;
+  std::lock_guard<std::mutex> lk(D->mu);
+  // buckets of the batch: (k, smallest lane-group width)
+  std::vector<HostSys> bucket[BDEG_MAX_K + 1][7];
+  for (auto &h : b->dev) {
+    HostSys c = h;
+    c.attempt = 0;
+    bucket[h.k][npad_log2_for(h.N)].push_back(c);
+  }
+  ScheduleTable best;
+  if (table_path) (void)schedule_read(table_path, best); // keep other buckets' entries
+  static const uint64_t COSTS[] = {128, 256, 512, 1024, 2048, 4096, 8192};
+  for (int k = 1; k <= BDEG_MAX_K; k++)
+    for (int g = 3; g <= 6; g++) {
+      const std::vector<HostSys> &sys = bucket[k][g];
+      if (sys.empty()) continue;
+      // the default schedule first: its sums are the reference every other
+      // schedule must reproduce exactly (same liftings, same candidates)
+      std::vector<SysAcc> ref, sums;
+      float ms_best = 0;
+      int rc = time_schedule(D, sys, nullptr, reps, &ms_best, &ref);
+      if (rc) return rc;
+      BucketSchedule pick;
+      pick.ms = ms_best;
+      for (int w = g; w <= std::min(6, g + 1); w++)
+        for (uint64_t cost : COSTS) {
+          ScheduleTable one;
+          one.e[k][g].npad_log2 = w;
+          one.e[k][g].unit_cost = cost;
+          one.any = true;
+          float ms = 0;
+          rc = time_schedule(D, sys, &one, reps, &ms, &sums);
+          if (rc) return rc;
+          for (size_t i = 0; i < ref.size(); i++)
+            if (sums[i].lo != ref[i].lo || sums[i].hi != ref[i].hi || sums[i].cells != ref[i].cells ||
+                sums[i].tie != ref[i].tie)
+              return BDEG_E_STATE; // a schedule changed a result: never persist it
+          if (ms < pick.ms) {
+            pick.ms = ms;
+            pick.npad_log2 = w;
+            pick.unit_cost = cost;
+          }
+        }
+      pick.systems = (int)sys.size();
+      if (pick.npad_log2 == 0) { // the default won: record it explicitly
+        pick.npad_log2 = g;
+        pick.unit_cost = 0;
+      }
+      best.e[k][g] = pick;
+      best.any = true;
+    }
+  if (table_path) {
+    const int rc = schedule_write(table_path, best);
+    if (rc) return rc;
+  }
+  return batch_setup(b, D, &best);
 }
 
 int bdeg_batch_destroy(bdeg_batch *b) {
@@ -513,10 +665,10 @@ int bdeg_batch_destroy(bdeg_batch *b) {
   if (D) {
     std::lock_guard<std::mutex> lk(D->mu);
     (void)hipStreamSynchronize(D->stream);
-    if (b->exec_pre) (void)hipGraphExecDestroy(b->exec_pre);
-    if (b->exec_enum) (void)hipGraphExecDestroy(b->exec_enum);
-    if (b->graph_pre) (void)hipGraphDestroy(b->graph_pre);
-    if (b->graph_enum) (void)hipGraphDestroy(b->graph_enum);
+    for (hipGraphExec_t x : {b->exec_pre, b->exec_enum, b->exec_retry})
+      if (x) (void)hipGraphExecDestroy(x);
+    for (hipGraph_t g : {b->graph_pre, b->graph_enum, b->graph_retry})
+      if (g) (void)hipGraphDestroy(g);
     if (b->ev_t0) (void)hipEventDestroy(b->ev_t0);
     if (b->ev_t1) (void)hipEventDestroy(b->ev_t1);
     if (b->ev_k0) (void)hipEventDestroy(b->ev_k0);

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/bdeg.h"
+#include "lifting.hpp"
 
 namespace bdeg {
 
@@ -23,6 +24,9 @@ struct SysDesc {
   int32_t lift_bits; // heights uniform in [0, 2^lift_bits)
   int32_t npad_log2; // lanes per point group: 8, 16, 32 or 64
   uint64_t lift_key; // counter-based lifting key for the current attempt
+  uint64_t seed;      // the system's lifting stream is (seed, sys_index, attempt)
+  uint32_t sys_index;
+  uint32_t pad;
 };
 
 // A work unit: the candidates whose top elements (colex) are exactly the set
@@ -47,13 +51,16 @@ struct SysAcc {
   uint64_t lo, hi;
   uint64_t cells;
   uint32_t tie;
-  uint32_t pad;
+  uint32_t attempt; // lifting draws made on the device beyond the host's (in-pass redraws)
 };
 
 // Device-wide counters (zeroed per run).
 struct DevCounters {
   uint64_t ridges, inner, sp_upd, pruned, leaves, tiles;
   uint64_t rsteps, lsteps, lempty; // wavefront loop iterations (ridge, leaf, leaf without candidates)
+  // the same work weighted by the points it touches (exact over systems of
+  // different N): N * inner, N * sp_upd, N * ridges, (N - k - 1) * leaves
+  uint64_t w_inner, w_spatial, w_ridges, w_leaves;
   uint32_t next_tile; // dynamic work queue head
   uint32_t error;     // a work unit exceeded its step budget (watchdog)
 };
@@ -86,8 +93,6 @@ void tile_interval(const Tile &t, int k, uint64_t *start, uint64_t *end);
 // order work units by decreasing cost and strip the costs
 void tiles_sorted(std::vector<TileC> &in, std::vector<Tile> &out);
 
-// ------------------------------------------------------------ lifting
-uint64_t lift_key(uint64_t seed, uint32_t sys_index, uint32_t attempt);
 
 // Device cell list: vertex masks of lower facets, appended through `count`
 // (facets beyond `cap` are counted, not stored).
@@ -137,6 +142,19 @@ int max_pivot_blocks(int k);
 // (cleared) hash set a.table.
 int launch_pivot_rehash(void *stream, const PivotArgs &a, const uint64_t *old, uint64_t n_old);
 
+// ------------------------------------------------------------ Extend (kernels_extend.hip)
+constexpr uint32_t EXTEND_TIE = 1;       // a lower face is not a simplex (the lifting is not generic)
+constexpr uint32_t EXTEND_ERR_SPAN = 2;  // the points do not span the space affinely
+constexpr uint32_t EXTEND_ERR_RANGE = 4; // an exact division failed (outside the certified widths)
+struct ExtendResult {
+  uint64_t mask; // the lower facet found (k + 1 points), 0 on failure
+  uint32_t flags;
+  uint32_t pad;
+};
+// One wavefront: a lower facet of the lifted points by exact supporting-
+// hyperplane rotations from the lowest point (N <= 64, k <= PIVOT_MAX_K).
+int launch_extend(void *stream, const int32_t *d_pts, const int64_t *d_hts, int N, int k, ExtendResult *d_out);
+
 // ------------------------------------------------------------ prefix pruning (kernels_prune.hip)
 constexpr int PRUNE_WMAX = 8; // widest prefix state tested (free spatial columns)
 struct PruneCounters {
@@ -175,8 +193,11 @@ constexpr int MODE_STATS = 1; // also count the work (profiling)
 constexpr int MODE_EMIT = 2;  // also list every lower facet (single-k kernels only)
 
 // host-side handle of one enumeration kernel instantiation
+// rerun (optional): rerun[0] != 0 when some system is redrawn in this pass,
+// rerun[1 + s] != 0 for the systems whose units are run (the others' units are
+// skipped); nullptr runs every unit.
 typedef void (*EnumFn)(const SysDesc *, const int32_t *, const int64_t *, const Tile *, uint32_t, SysAcc *,
-                       DevCounters *, CellSink);
+                       DevCounters *, CellSink, const uint32_t *);
 
 struct LaunchShape {
   int blocks = 0;
@@ -184,6 +205,7 @@ struct LaunchShape {
   bool single = false; // every unit launched has N > 32 points: one point group per wavefront
   int mode = MODE_PLAIN;
   CellSink sink{nullptr, 0, nullptr}; // MODE_EMIT only
+  const uint32_t *rerun = nullptr;    // in-pass redraw round: gate and per-system flags
 };
 // point groups per wavefront for N points: 64 / (smallest power of two >= N, at least 8)
 inline int groups_for(int N) { return N <= 8 ? 8 : N <= 16 ? 4 : N <= 32 ? 2 : 1; }
@@ -195,6 +217,14 @@ int launch_lift(void *stream, const SysDesc *d_sys, const int32_t *d_active, int
                 int64_t *d_heights);
 int launch_clear(void *stream, SysAcc *d_acc, int n_sys, DevCounters *d_cnt, int n_cnt);
 int launch_clear_list(void *stream, SysAcc *d_acc, const int32_t *d_list, int n);
+// Start of a replayable seeded pass: every system back to attempt 0 (lifting
+// key, cleared sums), counter blocks and redraw gates cleared.
+int launch_reset(void *stream, SysDesc *d_sys, SysAcc *d_acc, int n_sys, DevCounters *d_cnt, int n_cnt,
+                 uint32_t *d_rerun, int rounds);
+// One in-pass redraw round: every system whose sums report a tie (and has
+// draws left) gets attempt + 1, a new lifting and cleared sums, and is marked
+// in rerun[1 + s]; rerun[0] is set when any is.
+int launch_retie(void *stream, SysDesc *d_sys, SysAcc *d_acc, int64_t *d_heights, int n_sys, uint32_t *d_rerun);
 int launch_enumerate(void *stream, const SysDesc *d_sys, const int32_t *d_pts,
                      const int64_t *d_heights, const Tile *d_tiles, uint32_t n_tiles, SysAcc *d_acc,
                      DevCounters *d_cnt, int kmin, int kmax, LaunchShape shape);

@@ -653,6 +653,13 @@ __device__ __forceinline__ void run_unit(const Tile &tl, const SysDesc &sd, cons
       atomicAdd((unsigned long long *)&cnt->lempty, (unsigned long long)cx.lempty);
       atomicAdd((unsigned long long *)&cnt->pruned, (unsigned long long)cx.pruned);
       atomicAdd((unsigned long long *)&cnt->tiles, 1ull);
+      // a unit belongs to one system, so weighting its counts by that
+      // system's point count is exact for batches of mixed N and k
+      const unsigned long long n = (unsigned long long)sd.N, t = (unsigned long long)(sd.N - sd.k - 1);
+      atomicAdd((unsigned long long *)&cnt->w_inner, n * cx.inner);
+      atomicAdd((unsigned long long *)&cnt->w_spatial, n * cx.sp_upd);
+      atomicAdd((unsigned long long *)&cnt->w_ridges, n * cx.ridges);
+      atomicAdd((unsigned long long *)&cnt->w_leaves, t * cx.leaves);
     }
   }
 }
@@ -669,10 +676,12 @@ template <int KLO, int KHI, int MODE, int GG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for_depth(KHI, GG))))
 enum_kernel(const SysDesc *__restrict__ sys, const int32_t *__restrict__ pts, const int64_t *__restrict__ hts,
             const Tile *__restrict__ tiles, uint32_t n_tiles, SysAcc *__restrict__ acc,
-            DevCounters *__restrict__ cnt, CellSink sink) {
+            DevCounters *__restrict__ cnt, CellSink sink, const uint32_t *__restrict__ rerun) {
   const int lane = lane_id();
   __shared__ Tally tallies[4]; // one per wavefront of the block (at most 256 threads)
   Tally *tally = &tallies[threadIdx.x >> 6];
+  // an in-pass redraw round with nothing to redraw ends at once (uniform load)
+  if (rerun && rerun[0] == 0) return;
   for (;;) {
     // Every lane takes part in the claim (lane 0 adds one, the others zero)
     // and lane 0's result is read by index, so the claimed unit is uniform by
@@ -683,6 +692,7 @@ enum_kernel(const SysDesc *__restrict__ sys, const int32_t *__restrict__ pts, co
     const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int32_t)claim, 0);
     if (t >= n_tiles) break;
     const Tile tl = tiles[t];
+    if (rerun && rerun[1 + tl.sys] == 0) continue; // this system's sums stand
     const SysDesc sd = sys[tl.sys];
     run_unit<KLO, KHI, MODE, GG>(tl, sd, pts, hts, acc, cnt, sink, tally);
   }

@@ -8,12 +8,6 @@
 namespace bdeg {
 namespace dev {
 
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 // heights of the listed systems (all systems when active == nullptr)
 __global__ void lift_kernel(const SysDesc *__restrict__ sys, const int32_t *__restrict__ active, int n_active,
                             int64_t *__restrict__ hts) {
@@ -22,41 +16,67 @@ __global__ void lift_kernel(const SysDesc *__restrict__ sys, const int32_t *__re
   const int sid = active ? active[s] : s;
   const SysDesc d = sys[sid];
   const int j = threadIdx.x;
-  if (j < d.N) {
-    const uint64_t z = mix64(d.lift_key + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull);
-    hts[d.ht_off + j] = (int64_t)(z >> (64 - d.lift_bits));
+  if (j < d.N) hts[d.ht_off + j] = lift_height(d.lift_key, j, d.lift_bits);
+}
+
+__device__ __forceinline__ void clear_acc(SysAcc *a, uint32_t attempt) {
+  a->lo = 0;
+  a->hi = 0;
+  a->cells = 0;
+  a->tie = 0;
+  a->attempt = attempt;
+}
+
+__device__ __forceinline__ void clear_counters(DevCounters *cnt) {
+  cnt->ridges = cnt->inner = cnt->sp_upd = cnt->pruned = cnt->leaves = cnt->tiles = 0;
+  cnt->rsteps = cnt->lsteps = cnt->lempty = 0;
+  cnt->w_inner = cnt->w_spatial = cnt->w_ridges = cnt->w_leaves = 0;
+  cnt->next_tile = 0;
+  cnt->error = 0;
+}
+
+// every system back to attempt 0; counters and redraw gates cleared
+__global__ void reset_kernel(SysDesc *__restrict__ sys, SysAcc *__restrict__ acc, int n_sys,
+                             DevCounters *__restrict__ cnt, int n_cnt, uint32_t *__restrict__ rerun, int rounds) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_sys) {
+    sys[i].lift_key = lift_key(sys[i].seed, sys[i].sys_index, 0);
+    clear_acc(&acc[i], 0);
   }
+  if (i < n_cnt) clear_counters(&cnt[i]);
+  if (i < rounds) rerun[(size_t)i * (n_sys + 1)] = 0;
+}
+
+// one in-pass redraw round (one thread per system; a system's heights are
+// rewritten by its own thread, at most 64 points)
+__global__ void retie_kernel(SysDesc *__restrict__ sys, SysAcc *__restrict__ acc, int64_t *__restrict__ hts,
+                             int n_sys, uint32_t *__restrict__ rerun) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_sys) return;
+  const SysAcc a = acc[s];
+  uint32_t act = 0;
+  if (a.tie && a.attempt + 1 < (uint32_t)BDEG_MAX_ATTEMPTS) {
+    SysDesc &d = sys[s];
+    const uint32_t att = a.attempt + 1;
+    d.lift_key = lift_key(d.seed, d.sys_index, att);
+    for (int j = 0; j < d.N; j++) hts[d.ht_off + j] = lift_height(d.lift_key, j, d.lift_bits);
+    clear_acc(&acc[s], att);
+    act = 1;
+    atomicOr(&rerun[0], 1u);
+  }
+  rerun[1 + s] = act;
 }
 
 __global__ void clear_kernel(SysAcc *__restrict__ acc, int n_sys, DevCounters *__restrict__ cnt_all, int n_cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_sys) {
-    acc[i].lo = 0;
-    acc[i].hi = 0;
-    acc[i].cells = 0;
-    acc[i].tie = 0;
-    acc[i].pad = 0;
-  }
-  if (i < n_cnt && cnt_all) {
-    DevCounters *cnt = cnt_all + i;
-    cnt->ridges = cnt->inner = cnt->sp_upd = cnt->pruned = cnt->leaves = cnt->tiles = 0;
-    cnt->rsteps = cnt->lsteps = cnt->lempty = 0;
-    cnt->next_tile = 0;
-    cnt->error = 0;
-  }
+  if (i < n_sys) clear_acc(&acc[i], 0);
+  if (i < n_cnt && cnt_all) clear_counters(cnt_all + i);
 }
 
 // clear the partial sums of the listed systems
 __global__ void clear_list_kernel(SysAcc *__restrict__ acc, const int32_t *__restrict__ list, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    SysAcc *a = &acc[list[i]];
-    a->lo = 0;
-    a->hi = 0;
-    a->cells = 0;
-    a->tie = 0;
-    a->pad = 0;
-  }
+  if (i < n) clear_acc(&acc[list[i]], 0);
 }
 
 } // namespace dev
@@ -76,6 +96,23 @@ int launch_clear(void *stream, SysAcc *d_acc, int n_sys, DevCounters *d_cnt, int
   if (n < 1) n = 1;
   hipLaunchKernelGGL(dev::clear_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, d_acc, n_sys,
                      d_cnt, n_cnt);
+  return hip_ok(hipGetLastError());
+}
+
+int launch_reset(void *stream, SysDesc *d_sys, SysAcc *d_acc, int n_sys, DevCounters *d_cnt, int n_cnt,
+                 uint32_t *d_rerun, int rounds) {
+  int n = n_sys > n_cnt ? n_sys : n_cnt;
+  if (rounds > n) n = rounds;
+  if (n < 1) n = 1;
+  hipLaunchKernelGGL(dev::reset_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, d_sys, d_acc, n_sys,
+                     d_cnt, n_cnt, d_rerun, rounds);
+  return hip_ok(hipGetLastError());
+}
+
+int launch_retie(void *stream, SysDesc *d_sys, SysAcc *d_acc, int64_t *d_heights, int n_sys, uint32_t *d_rerun) {
+  if (n_sys <= 0) return BDEG_OK;
+  hipLaunchKernelGGL(dev::retie_kernel, dim3((n_sys + 255) / 256), dim3(256), 0, (hipStream_t)stream, d_sys, d_acc,
+                     d_heights, n_sys, d_rerun);
   return hip_ok(hipGetLastError());
 }
 
@@ -171,7 +208,7 @@ int launch_enumerate(void *stream, const SysDesc *d_sys, const int32_t *d_pts, c
   const uint64_t need = ((uint64_t)n_tiles + wpb - 1) / wpb;
   if ((uint64_t)blocks > need) blocks = (int)need;
   hipLaunchKernelGGL(f, dim3(blocks), dim3(wpb * 64), 0, (hipStream_t)stream, d_sys, d_pts, d_heights, d_tiles,
-                     n_tiles, d_acc, d_cnt, shape.sink);
+                     n_tiles, d_acc, d_cnt, shape.sink, shape.rerun);
   return hip_ok(hipGetLastError());
 }
 

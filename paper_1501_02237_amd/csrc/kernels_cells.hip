@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(256) cell_normals_kernel(const uint64_t *__res
 // unrolled code; the matrix lives in private memory).  Cells of such systems
 // are few next to their candidates, and unrolled instances this deep take
 // minutes to compile.
-constexpr int DEEP_K_MAX = BDEG_MAX_K;
+constexpr int DEEP_K_MAX = PIVOT_MAX_K; // the walk's cells reach k = 24
 __global__ void __launch_bounds__(256) cell_normals_deep_kernel(const uint64_t *__restrict__ masks, uint64_t n,
                                                                 const int32_t *__restrict__ pts,
                                                                 const int64_t *__restrict__ hts, int N, int K,
@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(256) cell_normals_deep_kernel(const uint64_t *
 int launch_cell_normals(void *stream, const uint64_t *d_masks, uint64_t n, const int32_t *d_pts,
                         const int64_t *d_hts, int N, int k, int64_t *d_num, uint64_t *d_den, uint32_t *d_err) {
   if (n == 0) return BDEG_OK;
-  if (k < 1 || k > BDEG_MAX_K || N < k + 1 || N > 64 || !d_masks || !d_pts || !d_hts || !d_num || !d_den || !d_err)
+  if (k < 1 || k > PIVOT_MAX_K || N < k + 1 || N > 64 || !d_masks || !d_pts || !d_hts || !d_num || !d_den || !d_err)
     return BDEG_E_ARG;
   const uint64_t blocks = (n + 255) / 256;
   if (blocks > 0x7FFFFFFFull) return BDEG_E_TOO_LARGE;

@@ -51,7 +51,69 @@ struct WalkResult {
   u128 nvol = 0;
   uint64_t cells = 0;
   bool tie = false;
+  uint64_t start = 0; // the start cell (the caller's, or the one Extend found)
 };
+
+// Cells of the walk with their inner normals (alpha, 1), alpha = num / den.
+struct CellNormals {
+  std::vector<uint64_t> masks;
+  std::vector<int64_t> num; // k per cell
+  std::vector<uint64_t> den;
+};
+
+// Extend on the device: a lower facet of the uploaded points and heights.
+int extend_device(Device *D, const int32_t *d_pts, const int64_t *d_hts, int N, int k, uint64_t *mask, bool *tie) {
+  ExtendResult *d_out = nullptr;
+  if (hipMalloc((void **)&d_out, sizeof(ExtendResult)) != hipSuccess) return BDEG_E_NOMEM;
+  ExtendResult r{};
+  int rc = launch_extend(D->stream, d_pts, d_hts, N, k, d_out);
+  if (!rc && (hipMemcpyAsync(&r, d_out, sizeof r, hipMemcpyDeviceToHost, D->stream) != hipSuccess ||
+              hipStreamSynchronize(D->stream) != hipSuccess))
+    rc = BDEG_E_DEVICE;
+  (void)hipFree(d_out);
+  if (rc) return rc;
+  if (r.flags & EXTEND_ERR_RANGE) return BDEG_E_OVERFLOW;
+  if (r.flags & EXTEND_ERR_SPAN) return BDEG_E_ARG;
+  *tie = (r.flags & EXTEND_TIE) != 0;
+  *mask = r.mask;
+  if (!*tie && __builtin_popcountll(r.mask) != k + 1) return BDEG_E_STATE;
+  return BDEG_OK;
+}
+
+// Inner normals of listed cells (the cell-list kernel of the enumeration path).
+int normals_device(Device *D, const int32_t *d_pts, const int64_t *d_hts, int N, int k, CellNormals &c) {
+  const uint64_t n = c.masks.size();
+  c.num.assign(n * k, 0);
+  c.den.assign(n, 0);
+  if (n == 0) return BDEG_OK;
+  uint64_t *d_masks = nullptr, *d_den = nullptr;
+  int64_t *d_num = nullptr;
+  uint32_t *d_err = nullptr;
+  int rc = BDEG_OK;
+  if (hipMalloc((void **)&d_masks, n * sizeof(uint64_t)) != hipSuccess ||
+      hipMalloc((void **)&d_den, n * sizeof(uint64_t)) != hipSuccess ||
+      hipMalloc((void **)&d_num, n * (size_t)k * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc((void **)&d_err, sizeof(uint32_t)) != hipSuccess)
+    rc = BDEG_E_NOMEM;
+  uint32_t err = 0;
+  if (!rc && (hipMemcpyAsync(d_masks, c.masks.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, D->stream) !=
+                  hipSuccess ||
+              hipMemcpyAsync(d_err, &err, sizeof err, hipMemcpyHostToDevice, D->stream) != hipSuccess))
+    rc = BDEG_E_DEVICE;
+  if (!rc) rc = launch_cell_normals(D->stream, d_masks, n, d_pts, d_hts, N, k, d_num, d_den, d_err);
+  if (!rc && (hipMemcpyAsync(c.num.data(), d_num, n * (size_t)k * sizeof(int64_t), hipMemcpyDeviceToHost,
+                             D->stream) != hipSuccess ||
+              hipMemcpyAsync(c.den.data(), d_den, n * sizeof(uint64_t), hipMemcpyDeviceToHost, D->stream) !=
+                  hipSuccess ||
+              hipMemcpyAsync(&err, d_err, sizeof err, hipMemcpyDeviceToHost, D->stream) != hipSuccess ||
+              hipStreamSynchronize(D->stream) != hipSuccess))
+    rc = BDEG_E_DEVICE;
+  for (void *p : {(void *)d_masks, (void *)d_den, (void *)d_num, (void *)d_err})
+    if (p) (void)hipFree(p);
+  if (!rc && (err & 1u)) rc = BDEG_E_DEVICE;   // a listed mask is not a (k+1)-subset
+  if (!rc && (err & 2u)) rc = BDEG_E_OVERFLOW; // a value outside the certified widths
+  return rc;
+}
 
 // Make room for `need` cells: a larger work list (the listed cells copied)
 // and a hash set of twice that many slots rebuilt from the old set (it holds
@@ -96,8 +158,11 @@ int grow(Device *D, WalkBuffers &b, PivotArgs &a, uint64_t need, uint32_t tail) 
 // set are grown to the level's worst case (every processed cell adds at most
 // k + 1 new ones), so a level never runs out of room; a probe sequence that
 // runs out anyway (PIVOT_ERR_FULL) restarts the walk with twice the room.
+// start == 0: the start cell is found by Extend; a tie there is returned as
+// a tie of the walk.  With `normals`, the cells and their inner normals are
+// returned too.
 int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k, uint64_t start,
-         std::vector<uint64_t> *cells_out, WalkResult &out) {
+         std::vector<uint64_t> *cells_out, WalkResult &out, CellNormals *normals = nullptr) {
   WalkBuffers b;
   if (hipMalloc((void **)&b.pts, (size_t)N * k * sizeof(int32_t)) != hipSuccess ||
       hipMalloc((void **)&b.hts, (size_t)N * sizeof(int64_t)) != hipSuccess ||
@@ -108,6 +173,18 @@ int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k,
     return BDEG_E_DEVICE;
   const int blocks = max_pivot_blocks(k);
   if (blocks <= 0) return BDEG_E_DEVICE;
+  if (start == 0) {
+    bool tie = false;
+    const int rc = extend_device(D, b.pts, b.hts, N, k, &start, &tie);
+    if (rc) return rc;
+    if (tie) {
+      out.tie = true;
+      return BDEG_OK;
+    }
+  }
+  out.start = start;
+  std::vector<uint64_t> own;
+  if (normals && !cells_out) cells_out = &own;
   for (uint64_t room = 1ull << 20;; room *= 2) {
     if (room > (1ull << 31)) return BDEG_E_NOMEM;
     PivotArgs a;
@@ -182,66 +259,13 @@ int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k,
       cells_out->clear();
       for (uint64_t m : slots)
         if (m) cells_out->push_back(m);
+      if (normals) {
+        normals->masks = *cells_out;
+        const int rc2 = normals_device(D, b.pts, b.hts, N, k, *normals);
+        if (rc2) return rc2;
+      }
     }
     return BDEG_OK;
-  }
-}
-
-// A start cell: point 0 and, in index order, every point that raises the
-// affine rank (fraction-free elimination of the difference rows, int128 with
-// overflow checks).  0 when the points do not span Z^k.
-uint64_t greedy_simplex(const int32_t *pts, int N, int k) {
-  std::vector<std::vector<__int128>> rows; // echelon rows, pivot column of row i is piv[i]
-  std::vector<int> piv;
-  std::vector<__int128> prevs;
-  uint64_t mask = 1;
-  for (int j = 1; j < N && (int)rows.size() < k; j++) {
-    std::vector<__int128> r(k);
-    for (int i = 0; i < k; i++) r[i] = (__int128)pts[(size_t)j * k + i] - pts[i];
-    // reduce against the echelon rows: r <- (p_t r - r[c_t] row_t) / p_{t-1}
-    __int128 prev = 1;
-    bool ok = true;
-    for (size_t t = 0; t < rows.size() && ok; t++) {
-      const int c = piv[t];
-      const __int128 p = rows[t][c], f = r[c];
-      for (int i = 0; i < k; i++) {
-        __int128 u, v, w;
-        if (__builtin_mul_overflow(p, r[i], &u) || __builtin_mul_overflow(f, rows[t][i], &v) ||
-            __builtin_sub_overflow(u, v, &w)) {
-          ok = false;
-          break;
-        }
-        r[i] = w / prev;
-      }
-      prev = p;
-    }
-    if (!ok) return 0;
-    int c = -1;
-    for (int i = 0; i < k; i++)
-      if (r[i] != 0) {
-        c = i;
-        break;
-      }
-    if (c < 0) continue; // affinely dependent on the chosen points
-    rows.push_back(r);
-    piv.push_back(c);
-    prevs.push_back(prev);
-    mask |= 1ull << j;
-  }
-  return (int)rows.size() == k ? mask : 0;
-}
-
-// Heights of the walk: 0 on the start cell, 1 + a counter-based draw in
-// [0, 2^bits) elsewhere, so the start cell is a lower facet.
-void walk_heights(uint64_t start, int N, uint64_t key, int bits, std::vector<int64_t> &h) {
-  h.assign(N, 0);
-  for (int j = 0; j < N; j++) {
-    if ((start >> j) & 1) continue;
-    uint64_t z = key + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z ^= z >> 31;
-    h[j] = 1 + (int64_t)(z >> (64 - bits));
   }
 }
 
@@ -254,12 +278,12 @@ using namespace bdeg;
 
 extern "C" {
 
-int bdeg_pivot_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, uint64_t start_mask,
-                      uint64_t cap, uint64_t *cell_masks, uint64_t *n_cells, bdeg_u128 *nvol, int32_t *tie) {
-  if (!points || !heights || !n_cells || !nvol || !tie || k < 1 || k > PIVOT_MAX_K || N < k + 1 || N > 64 ||
-      (cap > 0 && !cell_masks))
+// Arguments of the walk's point-set entry points: shape, |h| < 2^40, the
+// device width certificate, and a start mask of k + 1 points (0: Extend).
+static int check_walk_points(const int32_t *points, const int64_t *heights, int N, int k, uint64_t start_mask) {
+  if (!points || !heights || k < 1 || k > PIVOT_MAX_K || N < k + 1 || N > 64) return BDEG_E_ARG;
+  if (start_mask != 0 && (__builtin_popcountll(start_mask) != k + 1 || (N < 64 && (start_mask >> N) != 0)))
     return BDEG_E_ARG;
-  if (__builtin_popcountll(start_mask) != k + 1 || (N < 64 && (start_mask >> N) != 0)) return BDEG_E_ARG;
   int64_t hmin = heights[0], hmax = heights[0];
   for (int j = 0; j < N; j++) {
     if (heights[j] >= (1ll << 40) || heights[j] <= -(1ll << 40)) return BDEG_E_ARG;
@@ -267,18 +291,80 @@ int bdeg_pivot_points(const int32_t *points, const int64_t *heights, int32_t N, 
     hmax = std::max(hmax, heights[j]);
   }
   if (!device_bounds_ok(points, N, k, (uint64_t)(hmax - hmin))) return BDEG_E_OVERFLOW;
+  return BDEG_OK;
+}
+
+int bdeg_pivot_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, uint64_t start_mask,
+                      uint64_t cap, uint64_t *cell_masks, uint64_t *n_cells, bdeg_u128 *nvol, int32_t *tie) {
+  if (!n_cells || !nvol || !tie || (cap > 0 && !cell_masks)) return BDEG_E_ARG;
+  int rc = check_walk_points(points, heights, N, k, start_mask);
+  if (rc) return rc;
   int st;
   Device *D = device_get(&st);
   if (!D) return st;
   std::lock_guard<std::mutex> lk(D->mu);
   std::vector<uint64_t> cells;
   WalkResult r;
-  int rc = walk(D, points, heights, N, k, start_mask, cap > 0 ? &cells : nullptr, r);
+  rc = walk(D, points, heights, N, k, start_mask, cap > 0 ? &cells : nullptr, r);
   if (rc) return rc;
   *tie = r.tie ? 1 : 0;
   *nvol = u128_out(r.nvol);
-  *n_cells = r.cells;
+  *n_cells = r.tie ? 0 : r.cells;
   if (cap > 0 && !r.tie) memcpy(cell_masks, cells.data(), std::min<uint64_t>(cap, cells.size()) * sizeof(uint64_t));
+  return BDEG_OK;
+}
+
+int bdeg_pivot_cells(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, uint64_t start_mask,
+                     uint64_t cap, uint64_t *cell_masks, int64_t *normal_num, uint64_t *normal_den,
+                     uint64_t *n_cells, bdeg_u128 *nvol, int32_t *tie) {
+  if (!n_cells || !nvol || !tie || (cap > 0 && (!cell_masks || !normal_num || !normal_den))) return BDEG_E_ARG;
+  int rc = check_walk_points(points, heights, N, k, start_mask);
+  if (rc) return rc;
+  int st;
+  Device *D = device_get(&st);
+  if (!D) return st;
+  std::lock_guard<std::mutex> lk(D->mu);
+  CellNormals cn;
+  WalkResult r;
+  rc = walk(D, points, heights, N, k, start_mask, nullptr, r, &cn);
+  if (rc) return rc;
+  *tie = r.tie ? 1 : 0;
+  *nvol = u128_out(r.nvol);
+  *n_cells = r.tie ? 0 : r.cells;
+  if (r.tie || cap == 0) return BDEG_OK;
+  if (cn.masks.size() != r.cells) return BDEG_E_STATE; // every processed cell is in the set exactly once
+  const uint64_t n = std::min<uint64_t>(cap, cn.masks.size());
+  memcpy(cell_masks, cn.masks.data(), n * sizeof(uint64_t));
+  memcpy(normal_num, cn.num.data(), n * (size_t)k * sizeof(int64_t));
+  memcpy(normal_den, cn.den.data(), n * sizeof(uint64_t));
+  return BDEG_OK;
+}
+
+int bdeg_extend_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, uint64_t *facet_mask,
+                       int32_t *tie) {
+  if (!facet_mask || !tie) return BDEG_E_ARG;
+  int rc = check_walk_points(points, heights, N, k, 0);
+  if (rc) return rc;
+  int st;
+  Device *D = device_get(&st);
+  if (!D) return st;
+  std::lock_guard<std::mutex> lk(D->mu);
+  int32_t *d_pts = nullptr;
+  int64_t *d_hts = nullptr;
+  if (hipMalloc((void **)&d_pts, (size_t)N * k * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc((void **)&d_hts, (size_t)N * sizeof(int64_t)) != hipSuccess)
+    rc = BDEG_E_NOMEM;
+  if (!rc && (hipMemcpy(d_pts, points, (size_t)N * k * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+              hipMemcpy(d_hts, heights, (size_t)N * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess))
+    rc = BDEG_E_DEVICE;
+  uint64_t mask = 0;
+  bool t = false;
+  if (!rc) rc = extend_device(D, d_pts, d_hts, N, k, &mask, &t);
+  if (d_pts) (void)hipFree(d_pts);
+  if (d_hts) (void)hipFree(d_hts);
+  if (rc) return rc;
+  *facet_mask = t ? 0 : mask;
+  *tie = t ? 1 : 0;
   return BDEG_OK;
 }
 
@@ -299,18 +385,18 @@ int bdeg_degree_pivot(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int
   const int N = n + 1, k = kp.k;
   if (k > PIVOT_MAX_K) return out->status = BDEG_E_TOO_LARGE;
   out->candidates = binom_u64(N, k + 1);
-  if (!device_bounds_ok(kp.pts.data(), N, k, (1ull << lift_bits) + 1)) return out->status = BDEG_E_OVERFLOW;
-  const uint64_t start = greedy_simplex(kp.pts.data(), N, k);
-  if (!start) return out->status = BDEG_E_OVERFLOW; // the int128 rank test overflowed
+  if (!device_bounds_ok(kp.pts.data(), N, k, (1ull << lift_bits) - 1)) return out->status = BDEG_E_OVERFLOW;
   int st;
   Device *D = device_get(&st);
   if (!D) return out->status = st;
   std::lock_guard<std::mutex> lk(D->mu);
-  std::vector<int64_t> h;
+  std::vector<int64_t> h(N);
   for (int attempt = 0; attempt < BDEG_MAX_ATTEMPTS; attempt++) {
-    walk_heights(start, N, lift_key(seed, 0, (uint32_t)attempt) ^ 0x5049564F54ull, lift_bits, h);
+    // the lifting bdeg_degree draws for the same seed (single-system stream)
+    const uint64_t key = lift_key(seed, 0, (uint32_t)attempt);
+    for (int j = 0; j < N; j++) h[j] = lift_height(key, j, lift_bits);
     WalkResult r;
-    int rc = walk(D, kp.pts.data(), h.data(), N, k, start, nullptr, r);
+    const int rc = walk(D, kp.pts.data(), h.data(), N, k, 0, nullptr, r);
     out->attempts = attempt + 1;
     if (rc) return out->status = rc;
     if (r.tie) continue;

@@ -62,7 +62,8 @@ uint64_t choose_max_cost(uint64_t total, int waves, uint64_t floor) {
 }
 
 
-void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t max_cost) {
+void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t max_cost,
+                      const ScheduleTable *sched) {
   job.sys.clear();
   job.pts.clear();
   job.tiles.clear();
@@ -80,13 +81,22 @@ void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t ma
     d.ht_off = ht;
     d.lift_bits = h.lift_bits;
     d.npad_log2 = npad_log2_for(h.N);
+    uint64_t cost = max_cost;
+    if (sched) {
+      const BucketSchedule &b = sched->e[h.k][d.npad_log2];
+      if (b.npad_log2 >= d.npad_log2 && b.npad_log2 <= 6) d.npad_log2 = b.npad_log2;
+      if (b.unit_cost > 0) cost = b.unit_cost;
+    }
     d.lift_key = lift_key(h.seed, (uint32_t)h.input_index, h.attempt);
+    d.seed = h.seed;
+    d.sys_index = (uint32_t)h.input_index;
+    d.pad = 0;
     job.sys.push_back(d);
     job.pts.insert(job.pts.end(), h.pts.begin(), h.pts.end());
     ht += h.N;
     job.kmax = std::max(job.kmax, h.k);
     job.kmin = std::min(job.kmin, h.k);
-    tiles_full(h.N, h.k, (uint32_t)s, max_cost, tc);
+    tiles_full(h.N, h.k, (uint32_t)s, cost, tc);
   }
   if (job.kmin > job.kmax) job.kmin = job.kmax;
   job_order_units(job, tc);
@@ -100,7 +110,8 @@ void job_order_units(Job &job, std::vector<TileC> &tc) {
     return (job.kmin != job.kmax && k <= MIXED_K_MAX) ? 0 : k;
   };
   std::stable_sort(tc.begin(), tc.end(), [&](const TileC &a, const TileC &b) {
-    const bool ga = single_group(job.sys[a.t.sys].N), gb = single_group(job.sys[b.t.sys].N);
+    // one point group per wavefront (64 lanes per group) runs in its own variant
+    const bool ga = job.sys[a.t.sys].npad_log2 == 6, gb = job.sys[b.t.sys].npad_log2 == 6;
     if (ga != gb) return ga < gb;
     const int ka = kclass(a), kb = kclass(b);
     if (ka != kb) return ka < kb;
@@ -110,7 +121,7 @@ void job_order_units(Job &job, std::vector<TileC> &tc) {
   job.granges.clear();
   for (size_t i = 0; i < tc.size(); i++) {
     job.tiles[i] = tc[i].t;
-    const bool g = single_group(job.sys[tc[i].t.sys].N);
+    const bool g = job.sys[tc[i].t.sys].npad_log2 == 6;
     const int kc = kclass(tc[i]);
     if (job.granges.empty() || job.granges.back().single != g || job.granges.back().kclass != kc) {
       Job::VariantRange r;
@@ -151,7 +162,8 @@ int job_upload(Job &job) {
     return rc;
   static_assert(sizeof(SysAcc) == 32, "SysAcc layout");
   if ((rc = grow(&job.d_acc, &job.cap_acc, job.sys.size()))) return rc;
-  if (!job.d_cnt && hipMalloc((void **)&job.d_cnt, MAX_RANGES * sizeof(DevCounters)) != hipSuccess)
+  if ((rc = grow(&job.d_rerun, &job.cap_rerun, (size_t)RETIE_ROUNDS * (job.sys.size() + 1)))) return rc;
+  if (!job.d_cnt && hipMalloc((void **)&job.d_cnt, CNT_BLOCKS * sizeof(DevCounters)) != hipSuccess)
     return BDEG_E_NOMEM;
   if (hipMemcpy(job.d_sys, job.sys.data(), job.sys.size() * sizeof(SysDesc), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(job.d_pts, job.pts.data(), job.pts.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
@@ -165,20 +177,35 @@ int job_upload(Job &job) {
 }
 
 int job_launch_pre(Job &job, hipStream_t stream) {
-  int rc = launch_clear(stream, job.d_acc, (int)job.sys.size(), job.d_cnt, MAX_RANGES);
+  int rc = launch_clear(stream, job.d_acc, (int)job.sys.size(), job.d_cnt, CNT_BLOCKS);
   if (rc) return rc;
   if (!job.explicit_heights) rc = launch_lift(stream, job.d_sys, nullptr, (int)job.sys.size(), job.d_hts);
   return rc;
 }
 
-int job_launch_enum(Job &job, hipStream_t stream) {
-  if (job.granges.size() > (size_t)MAX_RANGES) return BDEG_E_STATE;
+int job_launch_reset(Job &job, hipStream_t stream) {
+  if (job.explicit_heights) return BDEG_E_STATE;
+  int rc = launch_reset(stream, job.d_sys, job.d_acc, (int)job.sys.size(), job.d_cnt, CNT_BLOCKS, job.d_rerun,
+                        RETIE_ROUNDS);
+  if (rc) return rc;
+  return launch_lift(stream, job.d_sys, nullptr, (int)job.sys.size(), job.d_hts);
+}
+
+int job_launch_retie(Job &job, hipStream_t stream, int round) {
+  if (round < 1 || round > RETIE_ROUNDS || job.explicit_heights) return BDEG_E_STATE;
+  return launch_retie(stream, job.d_sys, job.d_acc, job.d_hts, (int)job.sys.size(),
+                      job.d_rerun + (size_t)(round - 1) * (job.sys.size() + 1));
+}
+
+int job_launch_enum(Job &job, hipStream_t stream, int round) {
+  if (job.granges.size() > (size_t)MAX_RANGES || round < 0 || round > RETIE_ROUNDS) return BDEG_E_STATE;
   for (size_t i = 0; i < job.granges.size(); i++) {
     const Job::VariantRange &r = job.granges[i];
     LaunchShape shape = job.shape;
     shape.single = r.single;
+    shape.rerun = round ? job.d_rerun + (size_t)(round - 1) * (job.sys.size() + 1) : nullptr;
     int rc = launch_enumerate(stream, job.d_sys, job.d_pts, job.d_hts, job.d_tiles + r.start, r.count, job.d_acc,
-                              job.d_cnt + i, r.klo, r.khi, shape);
+                              job.d_cnt + (size_t)round * MAX_RANGES + i, r.klo, r.khi, shape);
     if (rc) return rc;
   }
   return BDEG_OK;
@@ -195,7 +222,7 @@ int job_launch(Job &job, hipStream_t stream, hipEvent_t e0, hipEvent_t e1) {
 
 int job_collect(Job &job, hipStream_t stream, std::vector<SysAcc> &acc, DevCounters *cnt) {
   acc.resize(job.sys.size());
-  DevCounters blocks[MAX_RANGES];
+  DevCounters blocks[CNT_BLOCKS];
   if (!acc.empty() &&
       hipMemcpyAsync(acc.data(), job.d_acc, acc.size() * sizeof(SysAcc), hipMemcpyDeviceToHost, stream) != hipSuccess)
     return BDEG_E_DEVICE;
@@ -213,6 +240,10 @@ int job_collect(Job &job, hipStream_t stream, std::vector<SysAcc> &acc, DevCount
     sum.lsteps += b.lsteps;
     sum.lempty += b.lempty;
     sum.tiles += b.tiles;
+    sum.w_inner += b.w_inner;
+    sum.w_spatial += b.w_spatial;
+    sum.w_ridges += b.w_ridges;
+    sum.w_leaves += b.w_leaves;
     sum.error |= b.error;
   }
   if (cnt) *cnt = sum;
@@ -227,6 +258,9 @@ void Job::release() {
   if (d_tiles) (void)hipFree(d_tiles);
   if (d_acc) (void)hipFree(d_acc);
   if (d_cnt) (void)hipFree(d_cnt);
+  if (d_rerun) (void)hipFree(d_rerun);
+  d_rerun = nullptr;
+  cap_rerun = 0;
   d_sys = nullptr;
   d_pts = nullptr;
   d_hts = nullptr;

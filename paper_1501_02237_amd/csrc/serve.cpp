@@ -205,6 +205,9 @@ void bdeg_server::start_attempt(Request *r) {
   d.lift_bits = r->hs.lift_bits;
   d.npad_log2 = npad_log2_for(d.N);
   d.lift_key = lift_key(r->hs.seed, 0u, r->hs.attempt); // the single-system stream
+  d.seed = r->hs.seed;
+  d.sys_index = 0;
+  d.pad = 0;
   (void)hipMemcpyAsync(d_sys + r->slot, &d, sizeof(SysDesc), hipMemcpyHostToDevice, stream);
   // units are taken round-robin across requests in small steps, so their
   // order within a request does not matter: no sort

@@ -159,19 +159,4 @@ void tiles_sorted(std::vector<TileC> &in, std::vector<Tile> &out) {
   for (size_t i = 0; i < in.size(); i++) out[i] = in[i].t;
 }
 
-// Counter-based lifting key: SplitMix64's finaliser (Steele, Lea, Flood 2014)
-// over (seed, system, attempt), tagged with a library constant.
-static inline uint64_t mix64(uint64_t z) {
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-uint64_t lift_key(uint64_t seed, uint32_t sys_index, uint32_t attempt) {
-  const uint64_t LIB_TAG = 0xB0E6D0C5B0E6D0C5ull;
-  uint64_t z = seed ^ LIB_TAG ^ ((uint64_t)(sys_index + 1) * 0x9E3779B97F4A7C15ull) ^
-               ((uint64_t)(attempt + 1) * 0xD1B54A32D192ED03ull);
-  return mix64(mix64(z));
-}
-
 } // namespace bdeg

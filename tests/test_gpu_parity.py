@@ -121,10 +121,11 @@ def test_ties_match_oracle(seed):
 
 
 @pytest.mark.parametrize("N,k,bits", [(16, 13, 16), (18, 13, 20), (17, 14, 16), (20, 14, 16), (18, 15, 12),
-                                       (19, 16, 12), (21, 16, 12), (24, 13, 16)])
+                                       (19, 16, 12), (21, 16, 12), (24, 13, 16), (20, 17, 12), (21, 17, 16),
+                                       (22, 18, 14), (23, 18, 16)])
 def test_nvol_points_deep_k(N, k, bits):
-    """k = 13..16 (single-k kernels beyond the mixed-k range), both lane-group
-    variants, against the oracle on identical heights."""
+    """k = 13..18 (single-k kernels beyond the mixed-k range, up to the
+    device's deepest k), against the oracle on identical heights."""
     P = _sparse_points(0xDEE + N, N, k, 0.25)
     H = gen.random_heights(0xDEF + N + k, N, bits)
     say("deep k", N, k, bits)
@@ -137,6 +138,92 @@ def test_single_candidate_and_empty_range():
     g = _same(P, [5, 1, 2, 3])
     assert g.nvol == 1
     assert bd.nvol_points(P, [5, 1, 2, 3], 1, 1).nvol == 0
+
+
+# ------------------------------------------------------------------ duplicate points
+def _cube(k):
+    import itertools
+
+    return [list(v) for v in itertools.product([0, 1], repeat=k)]
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("which", ["origin", "vertex"])
+def test_duplicate_points_equal_heights_tie(k, which):
+    """A point repeated with the same height (v_i = v_j, or v_i = 0) lies on
+    every lower facet through its twin: a non-generic lower face, so the tie
+    flag is set, as the oracle says.  Cube vertices are vertices of the hull,
+    so every copy is on the lower hull."""
+    P = _cube(k)
+    j = 0 if which == "origin" else len(P) - 1
+    P = P + [list(P[j])]
+    H = gen.random_heights(0xD0B + k, len(P), 16)
+    H[-1] = H[j]
+    say("duplicate equal heights", k, which)
+    g = _same(np.array(P, dtype=np.int64), H)
+    assert g.tie
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("which", ["origin", "vertex", "inner"])
+def test_duplicate_points_unequal_heights(k, which):
+    """A repeated point with a different height: the higher copy is never on a
+    lower facet, so the result is that of the set without it (no tie)."""
+    P = _cube(k) + [[1] * (k - 1) + [0]]
+    j = {"origin": 0, "vertex": len(P) - 2, "inner": len(P) - 1}[which]
+    if which == "inner":  # a point strictly inside, repeated
+        P = [[2 * x for x in v] for v in _cube(k)] + [[1] * k]
+        j = len(P) - 1
+    base = np.array(P, dtype=np.int64)
+    Hb = gen.random_heights(0xD0C + k, len(P), 16)
+    P2 = np.vstack([base, base[j:j + 1]])
+    for up in (True, False):  # the copy above or below its twin
+        H2 = np.append(Hb, Hb[j] + (12345 if up else -12345))
+        say("duplicate unequal heights", k, which, up)
+        g = _same(P2, H2)
+        assert not g.tie
+        want = oracle.nvol_range(base, Hb if up else np.where(np.arange(len(P)) == j, H2[-1], Hb))
+        assert g.nvol == want.nvol
+
+
+# ------------------------------------------------------------------ near the certified widths
+def _cert_margin(P, span):
+    """log2 of the slack of the device's width certificate for points P and
+    height span (positive: inside).  Spatial Hadamard bound Hs (the smaller of
+    its row- and column-wise forms) below 2^31, and (k+1) span Hs below 2^60."""
+    import math
+
+    P = np.asarray(P, dtype=np.int64)
+    N, k = P.shape
+    rows = sorted((1 + int((r * r).sum()) for r in P), reverse=True)[: k + 1]
+    h2_rows = math.prod(rows)
+    h2_cols = (k + 1) ** (k + 1) * math.prod(max(1, int(abs(P[:, i]).max())) ** 2 for i in range(k))
+    h2 = min(h2_rows, h2_cols)
+    return min(62 - math.log2(h2), 120 - math.log2(((k + 1) * max(span, 1)) ** 2 * h2)) / 2
+
+
+@pytest.mark.parametrize("k,c,bits", [(2, 1, 39), (3, 12, 39), (4, 12, 36), (5, 9, 33), (5, 6, 36), (6, 2, 39),
+                                      (7, 2, 36), (8, 1, 39)])
+def test_heights_near_the_certified_width(k, c, bits):
+    """Heights up to 2^39 in magnitude (the entry point takes |h| < 2^40) and
+    point sets whose Hadamard bound leaves little room: the split 64-bit
+    height arithmetic on the device agrees with the oracle's int128."""
+    N = 3 * k + 4
+    rng = gen.stream(0xCE27, k * 100 + c, gen.PURPOSE_MATRIX)
+    from sympy import Matrix as M
+
+    while True:
+        P = [[0] * k] + [[rng.uniform_int(-c, c) for _ in range(k)] for _ in range(N - 1)]
+        if M(P).rank() == k:
+            break
+    P = np.array(P, dtype=np.int64)
+    H = gen.random_heights(0xCE28 + k, N, bits) - (1 << (bits - 1))
+    H[0] = -(1 << bits) + 1 if bits < 40 else H[0]
+    span = int(H.max() - H.min())
+    margin = _cert_margin(P, span)
+    say("near width", k, c, bits, "margin bits", round(margin, 2))
+    assert 0 < margin < 17
+    _same(P, H)
 
 
 def test_nvol_points_bound_rejected():
@@ -290,6 +377,7 @@ def test_prepared_batch_graph_replays():
             assert [_gres(r) for r in res] == expect
             st = b.stats()
             assert st["kernel_ms"] > 0
+            assert st["captured"] == 1  # the pass replays its captured graphs
         st = b.profile()
         assert st["tiles"] > 0 and st["leaves"] > 0
         b.run()  # the profiling pass leaves the captured pass intact
@@ -345,6 +433,57 @@ def test_cfg3_batch_4096():
         assert (r["k"], r["comps"], r["nvol"]) == (e["k"], e["comps"], e["nvol"]), e["index"]
 
 
+def test_prepared_batch_redraws_ties_inside_the_graph():
+    """4-bit heights make ties frequent: the captured pass redraws the tied
+    systems' liftings itself (up to three rounds), so each replay gives
+    exactly the one-shot results, attempts and cell counts included, and
+    reports the systems it redrew."""
+    mats = [gen.quiver_matrix(0x5EED0303, i, 12 + i % 9, 4 + i % 4, 2, 3) for i in range(40)]
+    alone = [bd.degree(A, seed=13, lift_bits=4, check=False) for A in mats]
+    assert sum(a["attempts"] > 1 for a in alone) >= 5
+    b = bd.Batch(mats, seed=13, lift_bits=4)
+    try:
+        for rep in range(3):
+            say("batch ties replay", rep)
+            b.run()
+            res = b.results()
+            st = b.stats()
+            assert st["captured"] == 1
+            assert st["redraws"] == sum(a["attempts"] > 1 for a in alone)
+            for a, r in zip(alone, res):
+                assert (r["status"], r["nvol"], r["attempts"], r["cells"]) == \
+                    (a["status"], a["nvol"], a["attempts"], a["cells"])
+    finally:
+        b.close()
+    for A, r in zip(mats[:8], res[:8]):
+        if r["status"] == 0:
+            assert _gres(r) == _ores(A)
+
+
+def test_batch_tuner_writes_a_table_and_keeps_results(tmp_path):
+    """The autotuner times every schedule of its grid on each (k, lane-group
+    width) bucket of the batch (each must reproduce the default's sums),
+    writes the fastest per bucket to a JSON table and applies it; the tuned
+    batch still equals the oracle."""
+    mats = _mixed(60, 0x5EED0304)
+    expect = [_ores(A) for A in mats]
+    path = str(tmp_path / "table.json")
+    b = bd.Batch(mats, seed=7, lift_bits=20)
+    try:
+        say("tuner: tuning")
+        b.tune(path, reps=2)
+        b.run()
+        assert [_gres(r) for r in b.results()] == expect
+        assert b.stats()["captured"] == 1
+    finally:
+        b.close()
+    table = json.load(open(path))
+    ks = {r["k"] for r in (bd.degree(A) for A in mats) if r["k"] >= 1}
+    assert {e["k"] for e in table["entries"]} == ks
+    for e in table["entries"]:
+        assert e["npad_min"] <= e["npad"] <= 6 and e["ms"] > 0 and e["systems"] > 0
+
+
 # ------------------------------------------------------------------ serving
 def test_serving_mix_equals_alone():
     """Requests submitted together (they share device steps) give exactly the
@@ -373,6 +512,46 @@ def test_serving_mix_equals_alone():
     for A, g in zip(mats[:12], got[:12]):
         assert _gres(g) == _ores(A)
     assert all(x is not None and x >= 0 for x in lat)
+
+
+def test_two_servers_at_once():
+    """Two engines open together (each with its own stream, slots and step
+    counters) serve interleaved requests; each result equals the one-shot
+    path."""
+    mats = [gen.quiver_matrix(0x5EED0403, i, 10 + i % 12, 5 + i % 4, 2, 3) for i in range(24)]
+    alone = [bd.degree(A, seed=9, lift_bits=20) for A in mats]
+    s1, s2 = bd.Server(32 << 20), bd.Server(32 << 20)
+    try:
+        t = [(s1 if i % 2 else s2).submit(A, seed=9, lift_bits=20) for i, A in enumerate(mats)]
+        say("two servers: submitted", len(t))
+        got = [(s1 if i % 2 else s2).wait(x) for i, x in enumerate(t)]
+    finally:
+        s1.close()
+        s2.close()
+    for a, g in zip(alone, got):
+        assert g["status"] == 0
+        assert (g["k"], g["comps"], g["nvol"], g["attempts"]) == (a["k"], a["comps"], a["nvol"], a["attempts"])
+
+
+def test_cfg5_serving_trace_against_oracle():
+    """The serving workload (n in [12, 32], k in [4, 9]): a stated subset of
+    its 4000 requests (the 20 largest and 400 seeded others, oracle values
+    in tests/golden/cfg5_expected.json) is submitted to one engine in trace
+    order with the arrival gaps compressed to zero, so that the requests
+    share device steps; every (k, components, nvol) equals the oracle's."""
+    exp = _golden("cfg5")
+    trace = gen.cfg5_trace(4000)
+    srv = bd.Server(256 << 20)
+    try:
+        tickets = [srv.submit(trace[e["index"]].system.A, seed=5, lift_bits=20) for e in exp]
+        say("cfg5: submitted", len(tickets))
+        got = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    assert max(e["k"] for e in exp) == 9 and max(e["n"] for e in exp) == 32
+    for e, g in zip(exp, got):
+        assert g["status"] == 0, e["index"]
+        assert (g["k"], g["comps"], g["nvol"]) == (e["k"], e["comps"], e["nvol"]), e["index"]
 
 
 def test_serving_small_budget_and_ties():

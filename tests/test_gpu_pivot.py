@@ -3,11 +3,11 @@
 The walk visits the cells of the regular subdivision across their facets
 from one start cell.  For a given lifting the cells are unique, so the walk's
 cell set must equal the oracle's lower facets bit for bit, and the volumes
-must agree.  The tests build their own start cell and heights (height 0 on an
-affinely independent set, so that set is a lower facet; positive seeded
-heights elsewhere), independently of the library's construction.  At sizes
-beyond the oracle the expected values are the exhaustive device path's and
-the paper's Table 4.
+must agree.  Some tests build their own start cell and heights (height 0 on
+an affinely independent set, so that set is a lower facet; positive seeded
+heights elsewhere); the others give raw seeded heights and let Extend find
+the start cell.  At sizes beyond the oracle the expected values are the
+exhaustive device path's and the paper's Table 4.
 """
 import json
 import os
@@ -125,3 +125,68 @@ def test_degree_pivot_table4(mk):
     say("table 4 by pivoting", mk)
     r = bd.degree_pivot(gen.master_space_matrix(m, k), seed=5, lift_bits=20)
     assert r["status"] == 0 and r["comps"] * r["nvol"] == PAPER["table4_degrees"][mk]
+
+
+# ------------------------------------------------------------------ Extend: the walk from a caller's lifting
+EXT_CASES = [(5, 1, 16), (8, 2, 16), (12, 3, 16), (16, 4, 20), (20, 5, 20), (24, 6, 20), (33, 4, 20),
+             (40, 3, 20), (18, 8, 16), (16, 10, 16), (64, 2, 24), (14, 12, 16), (29, 8, 20)]
+
+
+@pytest.mark.parametrize("N,k,bits", EXT_CASES)
+def test_extend_finds_one_of_the_oracles_cells(N, k, bits):
+    """Extend on raw seeded heights (no constructed zeros): the facet it
+    returns is one of the oracle's lower facets for the same lifting."""
+    P = _points(0x9B1 + N, N, k)
+    H = gen.random_heights(0x9B2 + N * 7 + k, N, bits)
+    say("extend", N, k, bits)
+    e = bd.extend_points(P, H)
+    o = oracle.cells_range(P, H)
+    assert not o.tie and not e["tie"]
+    assert e["mask"] in {int(m) for m in o.masks}
+
+
+@pytest.mark.parametrize("N,k,bits", EXT_CASES + [(12, 2, 1), (10, 3, 1), (16, 3, 2), (9, 2, 2), (20, 4, 3)])
+def test_walk_from_extend_matches_oracle_cells_and_normals(N, k, bits):
+    """The walk from Extend's facet, on a random lifting of the caller: its
+    cells with their inner normals (mask, numerators, denominator) equal the
+    oracle's lower facets bit for bit; with 1-3-bit heights the lifting is
+    not generic and both report the tie."""
+    P = _points(0x9B3 + N, N, k)
+    H = gen.random_heights(0x9B4 + N * 7 + k, N, bits)
+    say("walk from extend", N, k, bits)
+    g = bd.pivot_cells(P, H)
+    o = oracle.cells_range(P, H)
+    assert g["tie"] == o.tie
+    if not o.tie:
+        assert g["cell_list"].as_set() == o.as_set()
+        assert g["nvol"] == sum(int(d) for d in o.den) and g["cells"] == len(o.masks)
+
+
+def test_walk_normals_deep_k_against_the_enumeration():
+    """k = 14 and 16 master-space systems (beyond the oracle's reach): the
+    walk's cells and normals from Extend equal the enumeration's cell list
+    for the same points and heights."""
+    for m, kk in ((2, 6), (3, 4)):
+        sub = bd.subdivision(gen.master_space_matrix(m, kk), seed=3, lift_bits=20, cap=1 << 16)
+        say("walk normals vs enumeration", m, kk, sub["k"])
+        g = bd.pivot_cells(sub["points"], sub["heights"])
+        assert not g["tie"]
+        assert g["cell_list"].as_set() == sub["cell_list"].as_set()
+        assert g["nvol"] == sub["nvol"]
+
+
+@pytest.mark.parametrize("idx", range(8))
+def test_degree_pivot_is_the_same_subdivision_as_degree(idx):
+    """bdeg_degree_pivot draws bdeg_degree's lifting and starts from Extend:
+    the same regular subdivision, so nvol, the cell count and the number of
+    draws agree (8-bit heights make redraws likely)."""
+    rng = gen.stream(0x9B5, idx, gen.PURPOSE_SIZES)
+    n = rng.uniform_int(10, 24)
+    k = rng.uniform_int(2, 7)
+    A = gen.quiver_matrix(0x9B6, idx, n, n - k, 2, 3)
+    bits = 8 if idx % 2 else 20
+    say("degree_pivot vs degree", idx, n, k, bits)
+    p = bd.degree_pivot(A, seed=idx, lift_bits=bits, check=False)
+    e = bd.degree(A, seed=idx, lift_bits=bits, check=False)
+    assert (p["status"], p["k"], p["comps"], p["nvol"], p["cells"], p["attempts"]) == \
+        (e["status"], e["k"], e["comps"], e["nvol"], e["cells"], e["attempts"])

@@ -243,3 +243,45 @@ def test_consistency_full_rank_and_errors():
         bd.consistency([[1], [1]], [0, 1])  # a zero right-hand side is outside (C*)^m
     with pytest.raises(bd.BdegError):
         bd.consistency([[1], [1]], [1, 1], tol=-1.0)
+
+
+def _cert_margin(P, span):
+    """log2 slack of the device width certificate (positive: inside): spatial
+    Hadamard bound Hs below 2^31 and (k+1) * span * Hs below 2^60."""
+    P = np.asarray(P, dtype=np.int64)
+    N, k = P.shape
+    rows = sorted((1 + int((r * r).sum()) for r in P), reverse=True)[: k + 1]
+    h2 = min(math.prod(rows), (k + 1) ** (k + 1) * math.prod(max(1, int(abs(P[:, i]).max())) ** 2 for i in range(k)))
+    return min(62 - math.log2(h2), 120 - math.log2(((k + 1) * max(span, 1)) ** 2 * h2)) / 2
+
+
+@pytest.mark.parametrize("k,c,bits", [(4, 12, 36), (4, 40, 32), (6, 3, 39), (6, 2, 39), (3, 12, 39)])
+def test_width_certificate_edge_on_the_host(k, c, bits):
+    """The host certificate decides before any device work: a point set just
+    outside it returns BDEG_E_OVERFLOW, one just inside passes the host
+    checks (and, with no GPU here, stops at BDEG_E_DEVICE); heights of
+    magnitude 2^40 are rejected as arguments."""
+    N = 3 * k + 4
+    rng = gen.stream(0xCE27, k * 100 + c, gen.PURPOSE_MATRIX)
+    while True:
+        P = [[0] * k] + [[rng.uniform_int(-c, c) for _ in range(k)] for _ in range(N - 1)]
+        if Matrix(P).rank() == k:
+            break
+    P = np.array(P, dtype=np.int64)
+    H = gen.random_heights(0xCE28 + k, N, bits) - (1 << (bits - 1))
+    H[0] = -(1 << bits) + 1
+    margin = _cert_margin(P, int(H.max() - H.min()))
+    code = bd.BDEG_OK
+    try:
+        bd.nvol_points(P, H)
+    except bd.BdegError as err:
+        code = err.code
+    if margin > 0:
+        assert code in (bd.BDEG_OK, bd.BDEG_E_DEVICE)  # computed, or no GPU here
+    else:
+        assert code == bd.BDEG_E_OVERFLOW
+    H2 = H.copy()
+    H2[1] = 1 << 40
+    with pytest.raises(bd.BdegError) as e:
+        bd.nvol_points(P, H2)
+    assert e.value.code == bd.BDEG_E_ARG
