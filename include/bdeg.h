@@ -67,6 +67,13 @@ typedef struct {
   uint64_t lo, hi;
 } bdeg_u128;
 
+/* Result of one system.  Beyond the three numbers the method defines (k,
+ * components, nvol) it reports what callers of batches and liftings need:
+ * a per-system status, the rank, the lifting draws used, the consistency
+ * flag, the candidates decided and the cells of the final lifting; the
+ * `reserved` word keeps the 128-bit fields 16-byte aligned.  Likewise every
+ * entry point that draws a lifting takes its height width `lift_bits` beside
+ * the seed (the results do not depend on either; only `attempts` does). */
 typedef struct {
   int32_t status;       /* BDEG_OK or a BDEG_E_* code for this system */
   int32_t k;            /* n - rank(A) */
@@ -122,7 +129,9 @@ int bdeg_degree(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int32_t l
  *   A_concat   the matrices back to back, system s is m[s] x n[s] row-major.
  *   m, n       count entries each.  out: count results (per-system status).
  * Returns BDEG_OK if every system succeeded, else the first failing code
- * (every out[s].status is still filled).
+ * (every out[s].status is still filled).  Each system draws its liftings from
+ * the same stream as a one-shot bdeg_degree call with this seed, so out[s]
+ * equals bdeg_degree's result for system s, attempts and cells included.
  */
 int bdeg_degree_batch(const int64_t *A_concat, const int32_t *m, const int32_t *n, int32_t count,
                       uint64_t seed, int32_t lift_bits, bdeg_result *out);

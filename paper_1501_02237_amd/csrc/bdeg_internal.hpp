@@ -25,7 +25,7 @@ struct SysDesc {
   int32_t npad_log2; // lanes per point group: 8, 16, 32 or 64
   uint64_t lift_key; // counter-based lifting key for the current attempt
   uint64_t seed;      // the system's lifting stream is (seed, sys_index, attempt)
-  uint32_t sys_index;
+  uint32_t sys_index; // stream index: 0 for every seeded system (one-shot, batch and served alike)
   uint32_t pad;
 };
 

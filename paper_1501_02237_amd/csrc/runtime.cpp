@@ -55,9 +55,8 @@ int default_waves(int kmin, int kmax, int waves_per_block) {
 // steps per candidate with k <= 18, stays below the device's signed 32-bit
 // budget count however large the job.
 uint64_t choose_max_cost(uint64_t total, int waves, uint64_t floor) {
-  constexpr uint64_t MAX_UNIT = 1ull << 26;
   uint64_t per = total / ((uint64_t)(waves > 0 ? waves : 1) * 16);
-  if (per > MAX_UNIT) per = MAX_UNIT;
+  if (per > MAX_UNIT_CANDIDATES) per = MAX_UNIT_CANDIDATES;
   return per < floor ? floor : per;
 }
 
@@ -87,9 +86,12 @@ void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t ma
       if (b.npad_log2 >= d.npad_log2 && b.npad_log2 <= 6) d.npad_log2 = b.npad_log2;
       if (b.unit_cost > 0) cost = b.unit_cost;
     }
-    d.lift_key = lift_key(h.seed, (uint32_t)h.input_index, h.attempt);
+    // every system draws from the single-system stream (index 0), so its
+    // liftings, and hence attempts and cells, do not depend on its position
+    // in a batch: a batched result equals the one-shot result exactly
+    d.lift_key = lift_key(h.seed, 0u, h.attempt);
     d.seed = h.seed;
-    d.sys_index = (uint32_t)h.input_index;
+    d.sys_index = 0;
     d.pad = 0;
     job.sys.push_back(d);
     job.pts.insert(job.pts.end(), h.pts.begin(), h.pts.end());

@@ -123,6 +123,9 @@ int job_collect(Job &job, hipStream_t stream, std::vector<SysAcc> &acc, DevCount
 // units: less prefix re-derivation per candidate); latency work (a lone small
 // request) passes a smaller one to spread over more wavefronts.
 constexpr uint64_t UNIT_FLOOR = 512;
+// Largest work unit: a unit's step budget, (k + 3) steps per candidate with
+// k <= 18, must fit the device's signed 32-bit budget count.
+constexpr uint64_t MAX_UNIT_CANDIDATES = 1ull << 26;
 uint64_t choose_max_cost(uint64_t total_candidates, int waves, uint64_t floor = UNIT_FLOOR);
 int default_waves(int kmin, int kmax, int waves_per_block);
 
