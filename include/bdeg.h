@@ -204,6 +204,29 @@ int bdeg_nvol_points(const int32_t *points, const int64_t *heights, int32_t N, i
                      uint64_t *cells);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): exactly
+ * bdeg_nvol_points (same arguments, results and errors), with every device
+ * buffer it uses -- the staged points and heights, the work units, the
+ * accumulator and the counters -- carved from one static device array of
+ * BDEG_NOALLOC_SCRATCH_BYTES that each GPU holds until the process ends.  It
+ * calls no hipMalloc or hipFree and no allocating device library routine
+ * (the host side of the plan reuses its buffers across calls).
+ *   Limit: at most BDEG_NOALLOC_MAX_UNITS work units.  The plan is coarsened
+ *   (larger units) until it fits; BDEG_E_TOO_LARGE when even units of 2^26
+ *   candidates are too many (more than about 8.8e12 candidates in the range).
+ *   Sharing: every call on one GPU uses that GPU's array, which keeps the last
+ *   call's contents (each call clears what must start at zero).  Calls through
+ *   this library are serialised by its device lock; any other work that
+ *   overlapped a call on the same array would race with it.
+ */
+#define BDEG_NOALLOC_MAX_UNITS (1 << 17)
+#define BDEG_NOALLOC_SCRATCH_BYTES ((size_t)BDEG_NOALLOC_MAX_UNITS * 16u + 16384u)
+int bdeg_nvol_points_noalloc(const int32_t *points, const int64_t *heights, int32_t N, int32_t k,
+                             uint64_t rank_lo, uint64_t rank_hi, bdeg_u128 *nvol, int32_t *tie,
+                             uint64_t *cells);
+
+/*
  * Cells of the regular subdivision (Section 4) with their inner normals:
  * the lower facets among the candidates whose colex rank lies in
  * [rank_lo, rank_hi), each with the unique inner normal (alpha, 1) of eq.

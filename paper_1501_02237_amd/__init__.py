@@ -32,6 +32,8 @@ MAX_K = 18
 MAX_ATTEMPTS = 16
 PIVOT_MAX_K = 24
 PRUNE_MAX_PREFIXES = 1 << 24
+NOALLOC_MAX_UNITS = 1 << 17
+NOALLOC_SCRATCH_BYTES = NOALLOC_MAX_UNITS * 16 + 16384
 U64_MAX = (1 << 64) - 1
 
 
@@ -99,6 +101,7 @@ def lib() -> ctypes.CDLL:
         "bdeg_batch_destroy": ([P], ctypes.c_int),
         "bdeg_batch_tune": ([P, ctypes.c_char_p, I32], ctypes.c_int),
         "bdeg_nvol_points": ([P, P, I32, I32, U64, U64, P, P, P], ctypes.c_int),
+        "bdeg_nvol_points_noalloc": ([P, P, I32, I32, U64, U64, P, P, P], ctypes.c_int),
         "bdeg_nvol_points_pruned": ([P, P, I32, I32, I32, P, P, P, P], ctypes.c_int),
         "bdeg_kernel_points": ([P, I32, I32, P, P, P, P], ctypes.c_int),
         "bdeg_consistency": ([P, I32, I32, P, ctypes.c_double, P, P, P], ctypes.c_int),
@@ -318,6 +321,21 @@ def nvol_points(points, heights, rank_lo: int = 0, rank_hi: int | None = None) -
                                 ctypes.byref(nv), ctypes.byref(tie), ctypes.byref(cells))
     if rc != BDEG_OK:
         raise BdegError(rc, "bdeg_nvol_points")
+    return VolumeRange(nv.value, bool(tie.value), cells.value)
+
+
+def nvol_points_noalloc(points, heights, rank_lo: int = 0, rank_hi: int | None = None) -> VolumeRange:
+    """bdeg_nvol_points_noalloc: nvol_points with every device buffer taken
+    from the library's static scratch array (no device allocation)."""
+    P = np.ascontiguousarray(np.asarray(points, dtype=np.int32))
+    H = np.ascontiguousarray(np.asarray(heights, dtype=np.int64))
+    N, k = P.shape
+    nv, tie, cells = U128(), ctypes.c_int32(), ctypes.c_uint64()
+    rc = lib().bdeg_nvol_points_noalloc(P.ctypes.data, H.ctypes.data, N, k, rank_lo,
+                                        U64_MAX if rank_hi is None else rank_hi, ctypes.byref(nv),
+                                        ctypes.byref(tie), ctypes.byref(cells))
+    if rc != BDEG_OK:
+        raise BdegError(rc, "bdeg_nvol_points_noalloc")
     return VolumeRange(nv.value, bool(tie.value), cells.value)
 
 

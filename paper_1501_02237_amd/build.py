@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libbdeg.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["algebra.cpp", "tiles.cpp", "runtime.cpp", "tune.cpp", "api.cpp", "serve.cpp", "kernels.hip",
            "kernels_mixed12.hip", "kernels_mixed7.hip", "kernels_cells.hip", "kernels_extend.hip", "pivot.cpp",
-           "kernels_prune.hip", "kernels_pivot_a.hip", "kernels_pivot_b.hip", "kernels_pivot_c.hip", "kernels_pivot_d.hip"] + [f"kernels_k{k}.hip" for k in range(18, 0, -1)]
+           "kernels_prune.hip", "noalloc.hip", "kernels_pivot_a.hip", "kernels_pivot_b.hip", "kernels_pivot_c.hip", "kernels_pivot_d.hip"] + [f"kernels_k{k}.hip" for k in range(18, 0, -1)]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -26,7 +26,7 @@ ARCH = "gfx950"
 def _flags(src: str) -> list[str]:
     f = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]
     f += [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-    if src.startswith(("kernels_pivot", "kernels_prune", "kernels_k", "kernels_mixed", "kernels_noalloc")):
+    if src.startswith(("kernels_pivot", "kernels_prune", "kernels_k", "kernels_mixed")):
         # the work-item claims of the enumeration, the walk and the prefix filter are atomic adds with a
         # per-lane value (one lane adds 1): a DPP scan instead of a 64-step scalar loop
         f += ["-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP"]

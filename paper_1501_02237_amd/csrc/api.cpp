@@ -153,8 +153,7 @@ int finish_device(Device *D, std::vector<HostSys> &dev, std::vector<bdeg_result>
   return BDEG_OK;
 }
 
-// Arguments of the point-set entry points: shape, |h| < 2^40, device bound.
-static int check_points(const int32_t *points, const int64_t *heights, int N, int k) {
+int check_points(const int32_t *points, const int64_t *heights, int N, int k) {
   if (!points || !heights || k < 1 || k > BDEG_MAX_K || N < k + 1 || N > 64) return BDEG_E_ARG;
   int64_t hmin = heights[0], hmax = heights[0];
   for (int j = 0; j < N; j++) {
@@ -167,8 +166,8 @@ static int check_points(const int32_t *points, const int64_t *heights, int N, in
 }
 
 // One caller point set with explicit heights, candidates of colex rank in [rank_lo, rank_hi).
-static void points_job(Job &job, const int32_t *points, const int64_t *heights, int N, int k, uint64_t rank_lo,
-                       uint64_t rank_hi) {
+void points_job(Job &job, const int32_t *points, const int64_t *heights, int N, int k, uint64_t rank_lo,
+                uint64_t rank_hi, uint64_t max_cost) {
   job.sys.clear();
   job.tiles.clear();
   SysDesc d;
@@ -190,7 +189,7 @@ static void points_job(Job &job, const int32_t *points, const int64_t *heights, 
   const uint64_t total = binom_u64(N, k + 1);
   const uint64_t hi = std::min(rank_hi, total), lo = std::min(rank_lo, hi);
   std::vector<TileC> tc;
-  tiles_range(N, k, 0, lo, hi, choose_max_cost(hi - lo, default_waves(k, k, 4)), tc);
+  tiles_range(N, k, 0, lo, hi, max_cost ? max_cost : choose_max_cost(hi - lo, default_waves(k, k, 4)), tc);
   job_order_units(job, tc);
 }
 
