@@ -31,7 +31,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_ALU = 256 * 4 * 16 * 2.4e9  # 32-bit integer VALU lane-ops/s: CUs x SIMDs x lanes x clock
+# 32-bit integer VALU lane-ops/s: 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz (the fp32 vector
+# rate, 157.3 TFLOP/s, is this many FMA lanes x 2 flops).  Plain 32-bit adds sustain 6.1e13 lane-ops/s
+# on the part (77 % of this, the clock under load); 32 x 32 -> 64 multiply-adds issue at half this rate,
+# which is why the op model counts each as 2 operations.
+PEAK_ALU = 256 * 4 * 32 * 2.4e9
 
 # HBM traffic of one headline enumeration launch (n = 36 system), from the
 # rocprofv3 FETCH_SIZE and WRITE_SIZE passes summarised in
@@ -41,8 +45,8 @@ PEAK_ALU = 256 * 4 * 16 * 2.4e9  # 32-bit integer VALU lane-ops/s: CUs x SIMDs x
 # work-unit sizing the counters were taken on: any change to the listed files
 # makes `traffic` null.
 TRAFFIC = {
-    "sources": ("enum_device.hpp", "exact_div.hpp", "kernels_k10.hip", "runtime.cpp", "bdeg_internal.hpp",
-                "lifting.hpp"),
+    "sources": ("enum_device.hpp", "enum_dense.hpp", "exact_div.hpp", "kernels_k10.hip", "runtime.cpp",
+                "bdeg_internal.hpp", "lifting.hpp"),
     "sha256": "",
     "fetch_kib": 0.0, "fetch_scale": 1.0,
     "write_kib": 0.0, "write_scale": 1.0,
@@ -66,15 +70,24 @@ def ops_per_launch(stats: dict) -> float:
     32 x 32 -> 64 multiply counts 2, a 64-bit add/shift 2):
       spatial residual entry  8   (two products, a 64-bit difference, a shift, the inverse multiply)
       height residual entry  24   (two 64-bit halves of two products each, shift-add, 64-bit inverse multiply, split)
-      leaf test per point    20   (two halves, carry fold, sign and zero tests)
-    Every node update runs on all N points of its system; a leaf tests the
-    N - k - 1 other points.  The counting kernel variant reports the counts
-    already weighted by each system's N (exact for batches of mixed sizes):
-    a ridge adds one spatial and one height entry per point, an inner node
-    one height entry and W - 1 spatial entries per point."""
+      lanes-as-points schedule:
+        leaf test per point  20   (two halves, carry fold, sign and zero tests)
+      lane-dense schedule (no ridges):
+        candidate set-up    198   (three spatial and three height 2 x 2 minors, 24 + 72; the 3 x 3 spatial
+                                   minor, 12; three 3 x 3 height minors in split limbs, 90)
+        test per point       19   (eight products, the low limbs' carry shift, the sign accumulation)
+    Every node update runs on all N points of its system; a leaf (a
+    candidate with D != 0) tests the N - k - 1 other points; the lane-dense
+    schedule sets up every candidate of its nodes, D = 0 or not.  The counting
+    kernel variant reports the counts already weighted by each system's N
+    (exact for batches of mixed sizes): a ridge adds one spatial and one
+    height entry per point, an inner node one height entry and W - 1 spatial
+    entries per point.  (When a launch mixes both schedules the leaf test is
+    counted at the smaller rate.)"""
     sp = stats["point_spatial"] + stats["point_ridges"]
     ht = stats["point_inner"] + stats["point_ridges"]
-    return 8.0 * sp + 24.0 * ht + 20.0 * stats["leaf_points"]
+    leaf = 19.0 if stats.get("dense_units", 0) > 0 else 20.0
+    return 8.0 * sp + 24.0 * ht + leaf * stats["leaf_points"] + 198.0 * stats.get("triples", 0)
 
 
 def batch_leg(bd, torch, gen, reps: int) -> dict:
@@ -309,6 +322,9 @@ def main():
                     help="run only this leg's timed steps and print its figures (for profiling)")
     ap.add_argument("--pruned", default="", choices=["", "headline", "large36"],
                     help="run only the prefix-pruned enumeration of this system and print its figures")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "points"],
+                    help="enumeration schedule of every leg (the headline is also run under the other one as an "
+                         "extra unless --no-extras)")
     ap.add_argument("--walk", default="",
                     help="M,K: run only the cell walk on the Table 4 system W_{M,K} and print its figures")
     a = ap.parse_args()
@@ -324,6 +340,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    sched = {"auto": bd.SCHED_AUTO, "points": bd.SCHED_POINTS}[a.schedule]
+    bd.set_schedule(sched)
     if a.calibrate_copy_mib > 0:
         src = torch.ones(a.calibrate_copy_mib << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -347,7 +365,9 @@ def main():
         return
     if a.only == "headline28":
         h = plain_leg(bd, torch, gen.cfg2_system(), a.steps, a.warmup)
-        h.pop("stats")
+        st = h.pop("stats")
+        h["work"] = {key: st[key] for key in ("tiles", "inner_nodes", "ridges", "leaves", "triples", "ridge_steps",
+                                              "leaf_steps", "dense_units", "pruned")}
         print(json.dumps(h), flush=True)
         return
 
@@ -358,14 +378,29 @@ def main():
     log(f"[bench] headline: {h['ms_step']:.3f} ms/step, kernel {h['kernel_ms']:.3f} ms, nvol={h['nvol']}, "
         f"{h['value']:.3e} cand/s, ops/launch {h['ops']:.3e}, ALU fraction {h['achieved'] / PEAK_ALU:.3f}")
     if a.only == "headline":
-        h.pop("stats")
+        st = h.pop("stats")
+        h["work"] = {key: st[key] for key in ("tiles", "inner_nodes", "ridges", "leaves", "triples", "ridge_steps",
+                                              "leaf_steps", "dense_units", "pruned")}
         print(json.dumps(h), flush=True)
         return
     st = h["stats"]
-    extra = {"nvol": h["nvol"], "kernel_ms": round(h["kernel_ms"], 4), "captured": h["captured"],
-             "leaves": st["leaves"], "ridges": st["ridges"], "inner_nodes": st["inner_nodes"],
-             "pruned": st["pruned"], "units": st["tiles"], "ops_per_launch": h["ops"]}
+    extra = {"schedule": a.schedule, "nvol": h["nvol"], "kernel_ms": round(h["kernel_ms"], 4),
+             "captured": h["captured"], "leaves": st["leaves"], "ridges": st["ridges"],
+             "inner_nodes": st["inner_nodes"], "triples": st["triples"], "pruned": st["pruned"],
+             "units": st["tiles"], "dense_units": st["dense_units"], "ops_per_launch": h["ops"]}
     if not a.no_extras:
+        # the same headline under the other schedule (same candidates, same result)
+        other = "points" if a.schedule == "auto" else "auto"
+        bd.set_schedule({"auto": bd.SCHED_AUTO, "points": bd.SCHED_POINTS}[other])
+        ho = plain_leg(bd, torch, s4, max(3, a.steps // 4), 1)
+        bd.set_schedule(sched)
+        assert ho["nvol"] == h["nvol"]
+        extra.update({f"{other}_schedule_kernel_ms": round(ho["kernel_ms"], 4),
+                      f"{other}_schedule_cand_per_s": ho["value"],
+                      f"{other}_schedule_alu_frac": ho["achieved"] / PEAK_ALU,
+                      f"{other}_schedule_ops_per_launch": ho["ops"]})
+        log(f"[bench] headline under the {other} schedule: kernel {ho['kernel_ms']:.3f} ms, "
+            f"{ho['value']:.3e} cand/s, ALU fraction {ho['achieved'] / PEAK_ALU:.3f}")
         # the n = 28 system, same measurement
         h2 = plain_leg(bd, torch, gen.cfg2_system(), a.steps, a.warmup)
         extra.update({"headline28_cand_per_s": h2["value"], "headline28_ms_step": round(h2["ms_step"], 4),

@@ -104,11 +104,33 @@ typedef struct {
   uint64_t point_spatial;     /* sum of N * spatial_updates */
   uint64_t point_ridges;      /* sum of N * ridges */
   uint64_t leaf_points;       /* sum of (N - k - 1) * leaves: points tested by the leaf tests */
+  /* lane-dense schedule (BDEG_SCHED_AUTO): it creates no ridges; its leaves
+     are the candidates with D != 0 it tested, ridge_steps its setup passes
+     and leaf_steps its test batches */
+  uint64_t triples;           /* candidates set up at nodes with three spatial columns left (any D) */
+  uint64_t dense_units;       /* work units run by the lane-dense kernel */
   float kernel_ms;            /* device time of the enumeration kernel, HIP events */
   float total_ms;             /* device time of the whole device pass (clear, lift, enumerate) */
   int32_t captured;           /* 1: the device pass replays captured HIP graphs; 0: plain launches */
   int32_t redraws;            /* systems whose tied lifting was redrawn inside the last device pass */
 } bdeg_stats;
+
+/* Enumeration schedule for the whole process (default BDEG_SCHED_AUTO).
+ * Both decide every candidate exactly and give identical results; they differ
+ * in how a wavefront's lanes are used.
+ *   BDEG_SCHED_AUTO    systems with k >= 3 whose minors the host certifies
+ *                      below 2^30 (spatial) and 2^59 (with heights) run in
+ *                      the lane-dense kernel: the depth-first walk stops with
+ *                      three spatial columns left, and each lane then tests a
+ *                      whole candidate against every point (cofactors by
+ *                      Sylvester's identity); all other systems as below.
+ *   BDEG_SCHED_POINTS  every system in the lanes-as-points kernel: lane j
+ *                      holds point j down to single candidates.
+ * Returns BDEG_E_ARG for another value.  Takes effect for work planned after
+ * the call (prepared batches keep the schedule they were created with). */
+#define BDEG_SCHED_AUTO 0
+#define BDEG_SCHED_POINTS 1
+int bdeg_set_schedule(int32_t schedule);
 
 /* Optional: select the HIP device (default: current device at first use).
  * Must precede every other call; BDEG_E_STATE if the library is already set up. */

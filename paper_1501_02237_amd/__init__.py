@@ -33,6 +33,8 @@ MAX_ATTEMPTS = 16
 PIVOT_MAX_K = 24
 PRUNE_MAX_PREFIXES = 1 << 24
 NOALLOC_MAX_UNITS = 1 << 17
+SCHED_AUTO = 0
+SCHED_POINTS = 1
 NOALLOC_SCRATCH_BYTES = NOALLOC_MAX_UNITS * 16 + 16384
 U64_MAX = (1 << 64) - 1
 
@@ -69,7 +71,8 @@ class Stats(ctypes.Structure):
         ("pruned", ctypes.c_uint64), ("leaves", ctypes.c_uint64), ("tiles", ctypes.c_uint64),
         ("ridge_steps", ctypes.c_uint64), ("leaf_steps", ctypes.c_uint64), ("empty_steps", ctypes.c_uint64),
         ("point_inner", ctypes.c_uint64), ("point_spatial", ctypes.c_uint64), ("point_ridges", ctypes.c_uint64),
-        ("leaf_points", ctypes.c_uint64), ("kernel_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
+        ("leaf_points", ctypes.c_uint64), ("triples", ctypes.c_uint64), ("dense_units", ctypes.c_uint64),
+        ("kernel_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
         ("captured", ctypes.c_int32), ("redraws", ctypes.c_int32),
     ]
 
@@ -91,6 +94,7 @@ def lib() -> ctypes.CDLL:
     P, I32, I64, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
     sig = {
         "bdeg_init": ([I32], ctypes.c_int),
+        "bdeg_set_schedule": ([I32], ctypes.c_int),
         "bdeg_degree": ([P, I32, I32, U64, I32, P], ctypes.c_int),
         "bdeg_degree_batch": ([P, P, P, I32, U64, I32, P], ctypes.c_int),
         "bdeg_batch_create": ([P, P, P, I32, U64, I32, P], ctypes.c_int),
@@ -147,6 +151,14 @@ def _mat(A) -> np.ndarray:
     if A.ndim != 2:
         raise ValueError("A must be a 2-D integer matrix (m x n)")
     return A
+
+
+def set_schedule(schedule: int) -> None:
+    """bdeg_set_schedule: SCHED_AUTO (lane-dense kernel for certified k >= 3
+    systems) or SCHED_POINTS (lanes as points everywhere)."""
+    rc = lib().bdeg_set_schedule(schedule)
+    if rc != BDEG_OK:
+        raise BdegError(rc, "bdeg_set_schedule")
 
 
 def degree(A, seed: int = 1, lift_bits: int = 20, check: bool = True) -> dict:

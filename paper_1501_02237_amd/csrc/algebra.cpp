@@ -204,8 +204,8 @@ KernelPoints kernel_points(const int64_t *A, int m, int n) {
 // <= sqrt(k+1) * max_j |p_ji|, so Hs^2 <= (k+1)^(k+1) * prod_i max(1, M_i)^2.
 // The smaller of the two certificates is used; point sets that are long in a
 // few directions only (a lattice with one long basis vector) pass the second.
-bool device_bounds_ok(const int32_t *pts, int N, int k, uint64_t height_span) {
-  const u128 lim = (u128)1 << 62;
+bool device_bounds_ok(const int32_t *pts, int N, int k, uint64_t height_span, int spatial_bits, int height_bits) {
+  const u128 lim = (u128)1 << (2 * spatial_bits);
   // row-wise: product of the k+1 largest (1 + |p_j|^2)
   std::vector<u128> f(N);
   for (int j = 0; j < N; j++) {
@@ -236,11 +236,11 @@ bool device_bounds_ok(const int32_t *pts, int N, int k, uint64_t height_span) {
   }
   const u128 h2 = std::min(h2_rows, h2_cols);
   if (h2 >= lim) return false;
-  // ((k+1) * span)^2 * Hs^2 < 2^120
+  // ((k+1) * span)^2 * Hs^2 < 2^(2 height_bits)
   u128 ks = (u128)(k + 1) * (u128)(height_span ? height_span : 1);
-  if (ks >= ((u128)1 << 60)) return false;
+  if (ks >= ((u128)1 << height_bits)) return false;
   u128 ks2 = ks * ks;
-  const u128 lim2 = (u128)1 << 120;
+  const u128 lim2 = (u128)1 << (2 * height_bits);
   if (h2 != 0 && ks2 > lim2 / h2) return false;
   return true;
 }

@@ -180,7 +180,12 @@ void points_job(Job &job, const int32_t *points, const int64_t *heights, int N, 
   d.lift_key = 0;
   d.seed = 0;
   d.sys_index = 0;
-  d.pad = 0;
+  int64_t hmin = heights[0], hmax = heights[0];
+  for (int j = 1; j < N; j++) {
+    hmin = std::min(hmin, heights[j]);
+    hmax = std::max(hmax, heights[j]);
+  }
+  d.flags = dense_ok(points, N, k, (uint64_t)(hmax - hmin)) ? SYS_DENSE : 0;
   job.sys.push_back(d);
   job.pts.assign(points, points + (size_t)N * k);
   job.heights.assign(heights, heights + N);
@@ -470,6 +475,8 @@ int bdeg_degree_batch(const int64_t *A_concat, const int32_t *m, const int32_t *
   return first_error(res);
 }
 
+int bdeg_set_schedule(int32_t schedule) { return schedule_set(schedule); }
+
 int bdeg_degree(const int64_t *A, int32_t m, int32_t n, uint64_t seed, int32_t lift_bits, bdeg_result *out) {
   if (!A || !out) return BDEG_E_ARG;
   return bdeg_degree_batch(A, &m, &n, 1, seed, lift_bits, out);
@@ -591,6 +598,8 @@ int bdeg_batch_profile(bdeg_batch *b) {
   b->stats.point_spatial = cnt.w_spatial;
   b->stats.point_ridges = cnt.w_ridges;
   b->stats.leaf_points = cnt.w_leaves;
+  b->stats.triples = cnt.triples;
+  b->stats.dense_units = cnt.dunits;
   return BDEG_OK;
 }
 
@@ -852,6 +861,7 @@ int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32
   if (!rc) {
     LaunchShape shape = job.shape;
     shape.single = single_group(N);
+    shape.dense = (job.sys[0].flags & SYS_DENSE) != 0;
     shape.mode = MODE_PLAIN;
     rc = launch_enumerate(D->stream, job.d_sys, job.d_pts, job.d_hts, d_units, pc.units, job.d_acc, job.d_cnt, k, k,
                           shape);

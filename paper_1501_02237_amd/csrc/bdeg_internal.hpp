@@ -26,7 +26,7 @@ struct SysDesc {
   uint64_t lift_key; // counter-based lifting key for the current attempt
   uint64_t seed;      // the system's lifting stream is (seed, sys_index, attempt)
   uint32_t sys_index; // stream index: 0 for every seeded system (one-shot, batch and served alike)
-  uint32_t pad;
+  uint32_t flags;     // SYS_DENSE
 };
 
 // A work unit: the candidates whose top elements (colex) are exactly the set
@@ -61,6 +61,9 @@ struct DevCounters {
   // the same work weighted by the points it touches (exact over systems of
   // different N): N * inner, N * sp_upd, N * ridges, (N - k - 1) * leaves
   uint64_t w_inner, w_spatial, w_ridges, w_leaves;
+  // lane-dense kernel: candidates set up at nodes with three spatial columns
+  // left (with or without D = 0), and the units it ran
+  uint64_t triples, dunits;
   uint32_t next_tile; // dynamic work queue head
   uint32_t error;     // a work unit exceeded its step budget (watchdog)
 };
@@ -77,8 +80,15 @@ KernelPoints kernel_points(const int64_t *A, int m, int n);
 
 // Device certification: every Bareiss quantity of the device path fits the
 // narrow types (spatial minors int32, height minors int64, products in 96 bits).
-// `height_span` is max(h) - min(h) over the points.
-bool device_bounds_ok(const int32_t *pts, int N, int k, uint64_t height_span);
+// `height_span` is max(h) - min(h) over the points.  Every spatial minor is
+// below 2^spatial_bits and every height minor below 2^height_bits (Hadamard).
+bool device_bounds_ok(const int32_t *pts, int N, int k, uint64_t height_span, int spatial_bits = 31,
+                      int height_bits = 60);
+// The lane-dense kernel (enum_dense.hpp) needs k >= 3, spatial minors
+// < 2^30 and height minors < 2^59; false also when the process asked for the
+// lanes-as-points schedule everywhere (bdeg_set_schedule).
+bool dense_ok(const int32_t *pts, int N, int k, uint64_t height_span);
+constexpr uint32_t SYS_DENSE = 1; // SysDesc.flags: units run in the lane-dense kernel
 
 // ------------------------------------------------------------ tiling
 uint64_t binom_u64(int n, int r); // saturates at UINT64_MAX
@@ -203,6 +213,7 @@ struct LaunchShape {
   int blocks = 0;
   int waves_per_block = 4;
   bool single = false; // every unit launched has N > 32 points: one point group per wavefront
+  bool dense = false;  // every unit launched belongs to a SYS_DENSE system: the lane-dense kernel
   int mode = MODE_PLAIN;
   CellSink sink{nullptr, 0, nullptr}; // MODE_EMIT only
   const uint32_t *rerun = nullptr;    // in-pass redraw round: gate and per-system flags
@@ -235,6 +246,7 @@ int device_cu_count();
 // a value outside int64.
 int launch_cell_normals(void *stream, const uint64_t *d_masks, uint64_t n, const int32_t *d_pts,
                         const int64_t *d_hts, int N, int k, int64_t *d_num, uint64_t *d_den, uint32_t *d_err);
-int max_enum_blocks(int kmin, int kmax, int waves_per_block, bool single); // occupancy-derived persistent grid
+int max_enum_blocks(int kmin, int kmax, int waves_per_block, bool single,
+                    bool dense = false); // occupancy-derived persistent grid
 
 } // namespace bdeg

@@ -1,0 +1,608 @@
+// Device code of the lane-dense enumeration kernel (included by the per-k
+// translation units, which instantiate it next to enum_device.hpp's kernel).
+#pragma once
+// What is computed is the same as in enum_device.hpp (Section 4, eqs.
+// "lower-face" and "simplex-vol", strict as in eq. "lower-d-face-again"):
+// for every candidate (k+1)-subset of the lifted points, whether every other
+// lifted point lies strictly above the hyperplane through it, and then
+// |det| of its spatial differences.  Only the schedule differs.
+//
+//   * A wavefront walks a work unit's subtree depth-first with lane j holding
+//     point j (one fraction-free Bareiss step per chosen point, as in
+//     enum_device.hpp), but stops with three spatial columns left: at a node
+//     with k - 2 points chosen, lane j holds (s0, s1, s2, h) of point j, the
+//     (T+1)-minors of the chosen difference rows bordered by point j.
+//   * The node's candidates are its triples {c1 > c2 > c3} below the lowest
+//     chosen point.  Lanes now stand for triples: each derives, from the
+//     node's rows c1, c2, c3 (in LDS), the triple's exact cofactors by
+//     Sylvester's identity -- the k x k spatial minor D and three height
+//     minors -- so that for every point j
+//         u_j = -s0_j H0 + s1_j H1 - s2_j H2 + h_j D = prev * M_j,
+//     where M_j is the (k+1)-minor of the candidate's rows and point j's row
+//     (point j's height over the candidate's hyperplane, times D) and prev is
+//     the node's last pivot.  A candidate is a lower facet exactly when
+//     sign(D) sign(prev) u_j > 0 for every point j off the candidate.
+//   * Triples with D != 0 are compacted into a ring of records in LDS; a test
+//     batch takes 64 records and loops over the points, every lane testing
+//     its own candidate against point j (row j is one broadcast LDS read), so
+//     all 64 lanes do the same useful work and consecutive points are
+//     independent chains.  A node with fewer than 64 candidates left splits
+//     each candidate's points over C = 2, 4, ... lanes.
+//   * The batch test is a filter on the high limbs (four multiply-adds per
+//     point), exact in what it rejects.  The rare survivors are decided
+//     exactly with lanes as points: a point strictly below rejects, else the
+//     zero count tells a lower facet (exactly the k + 1 vertices vanish) from
+//     a tie.
+//
+// Widths (certified on the host for these systems: spatial minors < 2^30,
+// height minors < 2^59): heights and height minors are split as
+// x = xh 2^29 + xl with 0 <= xl < 2^29, so every product is a signed
+// 32 x 32 -> 64 multiply-add; the low limbs of u_j sum to less than 2^61 and
+// the high limbs to less than 2^62.  u_j < 0 exactly when its high part
+// (with the low part's carry) is negative.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bdeg_internal.hpp"
+#include "enum_device.hpp"
+#include "exact_div.hpp"
+
+namespace bdeg {
+namespace dev {
+
+constexpr int DENSE_LIMB = 29;
+constexpr int64_t DENSE_LMASK = (1ll << DENSE_LIMB) - 1;
+constexpr int DENSE_RING = 128; // candidate records per wavefront (a power of two >= 2 * 64)
+
+// Per-wavefront LDS: the current node's point rows and the record ring.
+struct alignas(16) DenseLds {
+  alignas(16) int32_t rows[64][8];        // s0, s1, s2, h (low word), hh, hl; two unused words keep rows 32-byte aligned
+  alignas(16) int32_t rec[DENSE_RING][8]; // kl0, kh0, kl1, kh1, kl2, kh2, d, vertices and REC_FITS
+  Tally tally;
+};
+
+template <int MODE>
+struct DCtx {
+  static constexpr bool stats = MODE == MODE_STATS;
+  static constexpr bool emit = MODE == MODE_EMIT;
+  int N, k, j;
+  uint64_t mask;   // work unit prefix
+  int L;           // prefix length
+  int c_lo, c_hi;  // sibling run at the first free level
+  uint64_t chosen; // chosen points of the current node
+  DenseLds *lds;
+  int head, nrec;  // record ring: first record and count (wave-uniform)
+  bool rows_fit;   // every height of the current node fits int32
+  int32_t left;    // watchdog budget (as in enum_device.hpp)
+  uint32_t inner, sp_upd, pruned, nodes, triples, leaves, setups, tests;
+  CellSink sink;
+};
+
+__device__ __forceinline__ void wave_sync_lds() {
+  // LDS written by some lanes is read by others of the same wavefront
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// (Hi 2^29 + Lo) / d for an exact multiple whose quotient fits int64 (e <= 29).
+__device__ __forceinline__ int64_t exdiv_limbs(int64_t Hi, int64_t Lo, const Div &d) {
+  const uint64_t y = ((uint64_t)Hi << (DENSE_LIMB - d.e)) + (uint64_t)(Lo >> d.e);
+  return (int64_t)(y * d.inv);
+}
+
+// Colex unranking of a 3-subset {c1 > c2 > c3}: rank = C(c1,3) + C(c2,2) + c3.
+// Compares 6 r with c (c-1) (c-2) (no division); r < C(64, 3).
+__device__ __forceinline__ void unrank3(uint32_t r, int *c1, int *c2, int *c3) {
+  const uint32_t r6 = 6u * r;
+  uint32_t a = 2;
+#pragma unroll
+  for (uint32_t step = 32; step >= 1; step >>= 1) {
+    const uint32_t x = a + step;
+    const uint32_t p = __umul24(__umul24(x, x - 1), x - 2);
+    if (x <= 63 && p <= r6) a = x;
+  }
+  const uint32_t rem6 = r6 - __umul24(__umul24(a, a - 1), a - 2); // 6 (C(c2,2) + c3)
+  uint32_t b = 1;
+#pragma unroll
+  for (uint32_t step = 32; step >= 1; step >>= 1) {
+    const uint32_t x = b + step;
+    if (x < a && 3u * __umul24(x, x - 1) <= rem6) b = x;
+  }
+  const uint32_t c6 = rem6 - 3u * __umul24(b, b - 1); // 6 c3, c3 < 64
+  *c1 = (int)a;
+  *c2 = (int)b;
+  *c3 = (int)((c6 * 10923u) >> 16);
+}
+
+__device__ __forceinline__ uint32_t c3_of(int c) { return (uint32_t)(c * (c - 1) * (c - 2) / 6); }
+__device__ __forceinline__ uint32_t c2_of(int c) { return (uint32_t)(c * (c - 1) / 2); }
+
+// a * M into the limb sums (M = Mh 2^29 + Ml, |a| < 2^30, |M| < 2^59)
+__device__ __forceinline__ void acc_limbs(int64_t &Hi, int64_t &Lo, int32_t a, int64_t M) {
+  Hi += (int64_t)a * (int32_t)(M >> DENSE_LIMB);
+  Lo += (int64_t)a * (int32_t)(M & DENSE_LMASK);
+}
+
+// A candidate record: its coefficients k0, k1, k2 split at bit 29
+// (k = kh 2^29 + kl, 0 <= kl < 2^29) as kl0, kh0, kl1, kh1, kl2, kh2, then d,
+// then the vertices c1 | c2 << 8 | c3 << 16, plus REC_FITS when every
+// |k_a| < 2^31.  A node row: s0, s1, s2, h (its low word: the height itself
+// when it fits int32), hh, hl.
+constexpr int REC_FITS = 1 << 24;
+
+// u_j = k0 s0 + k1 s1 + k2 s2 + d h exactly, as (hi, lo) with
+// u = 2^29 hi + (lo mod 2^29): every product is a 32 x 32 -> 64 multiply-add
+// (|s|, |d| < 2^30; |k|, |h| < 2^59), the low limbs sum below 2^61 and the
+// high limbs below 2^62.
+struct UVal {
+  int64_t hi, lo;
+};
+__device__ __forceinline__ UVal u_exact(const int32_t *rc, int32_t s0, int32_t s1, int32_t s2, int32_t hh,
+                                        int32_t hl) {
+  const int64_t lo = (int64_t)s0 * rc[0] + (int64_t)s1 * rc[2] + (int64_t)s2 * rc[4] + (int64_t)hl * rc[6];
+  UVal u;
+  u.hi = (lo >> DENSE_LIMB) + (int64_t)s0 * rc[1] + (int64_t)s1 * rc[3] + (int64_t)s2 * rc[5] + (int64_t)hh * rc[6];
+  u.lo = lo;
+  return u;
+}
+
+// Exact decision of one candidate that no point lies strictly below, with
+// lanes as points: a lower facet when exactly its k + 1 vertices vanish, a
+// tie otherwise.
+template <class CX>
+__device__ __forceinline__ void decide_exact(CX &cx, const int32_t *rc) {
+  const int lane = lane_id();
+  const int32_t *row = cx.lds->rows[lane];
+  const UVal u = u_exact(rc, row[0], row[1], row[2], row[4], row[5]);
+  const bool on = u.hi == 0 && (u.lo & DENSE_LMASK) == 0;
+  const uint64_t zero = ballot(on && lane < cx.N);
+  const uint64_t below = ballot(u.hi < 0 && lane < cx.N);
+  if (below) return; // (the batch test is exact: cannot happen)
+  const int vtx = rc[7];
+  const int c1 = vtx & 255, c2 = (vtx >> 8) & 255, c3 = (vtx >> 16) & 255;
+  const uint64_t verts = cx.chosen | (1ull << c1) | (1ull << c2) | (1ull << c3);
+  if (zero != verts) {
+    if (lane == 0) cx.lds->tally.tie = 1;
+    return;
+  }
+  const int32_t d = rc[6];
+  if (lane == 0) {
+    cx.lds->tally.acc += (unsigned long long)(d < 0 ? -(int64_t)d : (int64_t)d);
+    cx.lds->tally.cells += 1;
+  }
+  if constexpr (CX::emit) emit_cell(cx, verts);
+}
+
+// Test the n oldest records of the ring (n <= 64), each over all points, its
+// points split over 2^logC lanes.
+template <class CX>
+__device__ __forceinline__ void test_batch(CX &cx, int n, int logC) {
+  const int lane = lane_id();
+  const int p = lane >> logC, q = lane & ((1 << logC) - 1);
+  const bool valid = p < n;
+  const int slot = (cx.head + (valid ? p : 0)) & (DENSE_RING - 1);
+  int32_t rc[8];
+  {
+    const int4 a = *(const int4 *)&cx.lds->rec[slot][0];
+    const int4 b = *(const int4 *)&cx.lds->rec[slot][4];
+    rc[0] = a.x, rc[1] = a.y, rc[2] = a.z, rc[3] = a.w, rc[4] = b.x, rc[5] = b.y, rc[6] = b.z, rc[7] = b.w;
+  }
+  // Exact test.  When the node's heights and every record's coefficients
+  // fit int32 (the common case), u_j is four products of 32-bit values,
+  // each below 2^61 in magnitude, summed exactly in int64; otherwise the
+  // two-limb form.  A candidate with some u_j < 0 is rejected.
+  const int iters = (cx.N + (1 << logC) - 1) >> logC; // rows past N are zero rows
+  const bool narrow = cx.rows_fit && ballot(valid && !(rc[7] & REC_FITS)) == 0;
+  int32_t neg = 0;
+  if (narrow) {
+    // each |k_a| < 2^31: the 32-bit values themselves (wrapping arithmetic
+    // rebuilds them exactly from the limbs)
+    const int32_t k0 = (int32_t)(((uint32_t)rc[1] << DENSE_LIMB) + (uint32_t)rc[0]);
+    const int32_t k1 = (int32_t)(((uint32_t)rc[3] << DENSE_LIMB) + (uint32_t)rc[2]);
+    const int32_t k2 = (int32_t)(((uint32_t)rc[5] << DENSE_LIMB) + (uint32_t)rc[4]);
+#pragma unroll 4
+    for (int it = 0; it < iters; it++) {
+      const int j = q + (it << logC); // < 64: 2^logC divides 64 and N <= 64
+      const int4 r = *(const int4 *)&cx.lds->rows[j][0];
+      const int64_t u = (int64_t)r.x * k0 + (int64_t)r.y * k1 + (int64_t)r.z * k2 + (int64_t)r.w * rc[6];
+      neg |= (int32_t)((uint64_t)u >> 32);
+    }
+  } else {
+#pragma unroll 2
+    for (int it = 0; it < iters; it++) {
+      const int j = q + (it << logC);
+      const int4 r = *(const int4 *)&cx.lds->rows[j][0];
+      const int2 hx = *(const int2 *)&cx.lds->rows[j][4];
+      const UVal u = u_exact(rc, r.x, r.y, r.z, hx.x, hx.y);
+      neg |= (int32_t)((uint64_t)u.hi >> 32);
+    }
+  }
+  if constexpr (CX::stats) cx.tests++;
+  const uint64_t rej = ballot(neg < 0);
+  const int C = 1 << logC;
+  const uint64_t gm = C >= 64 ? ~0ull : ((1ull << C) - 1);
+  const bool surv = valid && q == 0 && ((rej >> (p << logC)) & gm) == 0;
+  uint64_t sm = ballot(surv);
+  while (sm) { // rare: no point strictly below this candidate (a cell or a tie)
+    const int l = __builtin_ctzll(sm);
+    sm &= sm - 1;
+    int32_t b[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) b[i] = rl32(rc[i], l);
+    decide_exact(cx, b);
+  }
+  cx.head = (cx.head + n) & (DENSE_RING - 1);
+  cx.nrec -= n;
+}
+
+// The triples of a node with three spatial columns left (k - 2 points
+// chosen, lowest `low`), within the work unit's constraints.
+template <int K, class CX>
+__device__ __forceinline__ void triple_stage(CX &cx, const St<3> &st, int low) {
+  constexpr bool S = CX::stats;
+  const int lane = lane_id();
+  // 1. the node's rows (s0, s1, s2, h as lo/hi words); whether every |h_j| < 2^31
+  {
+    const int64_t h = ((int64_t)st.H1 << 31) + (int64_t)st.H0;
+    int4 r;
+    r.x = st.s[0], r.y = st.s[1], r.z = st.s[2], r.w = (int32_t)(uint32_t)h;
+    *(int4 *)&cx.lds->rows[lane][0] = r;
+    int2 hx;
+    hx.x = (int32_t)(h >> DENSE_LIMB), hx.y = (int32_t)(h & DENSE_LMASK);
+    *(int2 *)&cx.lds->rows[lane][4] = hx;
+    cx.rows_fit = ballot(h != (int64_t)(int32_t)h) == 0;
+  }
+  wave_sync_lds();
+  // 2. colex ranks of the triples allowed below this node
+  constexpr int P = K - 2; // position of c1 among the candidate's elements
+  uint32_t r_lo = 0, r_hi = 0;
+  {
+    uint64_t below = cx.mask & ((1ull << low) - 1);
+    if (cx.L < P) {
+      r_hi = c3_of(low);
+    } else if (cx.L == P) {
+      const int lo = max(cx.c_lo, 2), hi = min(cx.c_hi, low - 1);
+      if (hi >= lo) r_lo = c3_of(lo), r_hi = c3_of(hi + 1);
+    } else {
+      const int f1 = 63 - __builtin_clzll(below);
+      below &= ~(1ull << f1);
+      const uint32_t base1 = c3_of(f1);
+      if (cx.L == P + 1) {
+        const int lo = max(cx.c_lo, 1), hi = min(cx.c_hi, f1 - 1);
+        if (hi >= lo) r_lo = base1 + c2_of(lo), r_hi = base1 + c2_of(hi + 1);
+      } else {
+        const int f2 = 63 - __builtin_clzll(below);
+        below &= ~(1ull << f2);
+        const uint32_t base2 = base1 + c2_of(f2);
+        if (cx.L == P + 2) {
+          const int lo = max(cx.c_lo, 0), hi = min(cx.c_hi, f2 - 1);
+          if (hi >= lo) r_lo = base2 + (uint32_t)lo, r_hi = base2 + (uint32_t)hi + 1;
+        } else {
+          const int f3 = 63 - __builtin_clzll(below);
+          r_lo = base2 + (uint32_t)f3, r_hi = r_lo + 1;
+        }
+      }
+    }
+  }
+  if constexpr (S) cx.nodes++;
+  if (r_hi <= r_lo) return;
+  const Div dv = make_div(st.prev);
+  const bool prevneg = st.prev < 0;
+  // 3. setup passes of 64 triples: cofactors, compaction of D != 0
+  for (uint32_t base = r_lo; base < r_hi; base += 64) {
+    if (!charge(cx, 1)) return;
+    const uint32_t r = base + (uint32_t)lane;
+    const bool act = r < r_hi;
+    int c1, c2, c3;
+    unrank3(act ? r : r_lo, &c1, &c2, &c3);
+    const int32_t *R1 = cx.lds->rows[c1], *R2 = cx.lds->rows[c2], *R3 = cx.lds->rows[c3];
+    const int4 a1 = *(const int4 *)R1, a2 = *(const int4 *)R2, a3 = *(const int4 *)R3;
+    const int2 x1 = *(const int2 *)(R1 + 4), x2 = *(const int2 *)(R2 + 4), x3 = *(const int2 *)(R3 + 4);
+    // heights split at bit 29: h = hh 2^29 + l, 0 <= l < 2^29
+    const int32_t hh1 = x1.x, l1 = x1.y, hh2 = x2.x, l2 = x2.y, hh3 = x3.x, l3 = x3.y;
+    const int32_t s01 = a1.x, s11 = a1.y, s21 = a1.z;
+    const int32_t s02 = a2.x, s12 = a2.y, s22 = a2.z;
+    const int32_t s03 = a3.x, s13 = a3.y, s23 = a3.z;
+    // 2 x 2 minors of rows c1, c2 (T+2 minors), spatial and with the height column
+    const int32_t m01 = exdiv32((int64_t)s01 * s12 - (int64_t)s11 * s02, dv);
+    const int32_t m02 = exdiv32((int64_t)s01 * s22 - (int64_t)s21 * s02, dv);
+    const int32_t m12 = exdiv32((int64_t)s11 * s22 - (int64_t)s21 * s12, dv);
+    const int64_t m0h = exdiv_limbs((int64_t)s01 * hh2 - (int64_t)hh1 * s02, (int64_t)s01 * l2 - (int64_t)l1 * s02, dv);
+    const int64_t m1h = exdiv_limbs((int64_t)s11 * hh2 - (int64_t)hh1 * s12, (int64_t)s11 * l2 - (int64_t)l1 * s12, dv);
+    const int64_t m2h = exdiv_limbs((int64_t)s21 * hh2 - (int64_t)hh1 * s22, (int64_t)s21 * l2 - (int64_t)l1 * s22, dv);
+    // 3 x 3 minors of rows c1, c2, c3 (T+3 minors) by expansion along row c3:
+    // the spatial one D first, then, with row c3 multiplied by the
+    // orientation sign(D) sign(prev) (every minor below is linear in it), the
+    // coefficients of u_j: k0 = -H0, k1 = H1, k2 = -H2 (H_a: column a deleted)
+    const int32_t D = exdiv32((int64_t)s03 * m12 - (int64_t)s13 * m02 + (int64_t)s23 * m01, dv);
+    const bool nz = act && D != 0;
+    if constexpr (S) {
+      cx.setups++;
+      cx.triples += (uint32_t)__builtin_popcountll(ballot(act));
+    }
+    const bool flip = (D < 0) != prevneg;
+    const int32_t P0 = flip ? -s03 : s03, P1 = flip ? -s13 : s13, P2 = flip ? -s23 : s23;
+    const int32_t Ph = flip ? -hh3 : hh3, Pl = flip ? -l3 : l3;
+    int64_t Hi, Lo;
+    Hi = (int64_t)(-Ph) * m12, Lo = (int64_t)(-Pl) * m12;
+    acc_limbs(Hi, Lo, -P1, m2h);
+    acc_limbs(Hi, Lo, P2, m1h);
+    const int64_t k0 = exdiv_limbs(Hi, Lo, dv); // -H0, columns s1, s2, h
+    Hi = (int64_t)Ph * m02, Lo = (int64_t)Pl * m02;
+    acc_limbs(Hi, Lo, P0, m2h);
+    acc_limbs(Hi, Lo, -P2, m0h);
+    const int64_t k1 = exdiv_limbs(Hi, Lo, dv); // H1, columns s0, s2, h
+    Hi = (int64_t)(-Ph) * m01, Lo = (int64_t)(-Pl) * m01;
+    acc_limbs(Hi, Lo, -P0, m1h);
+    acc_limbs(Hi, Lo, P1, m0h);
+    const int64_t k2 = exdiv_limbs(Hi, Lo, dv); // -H2, columns s0, s1, h
+    const int32_t d = flip ? -D : D;
+    const uint64_t m = ballot(nz);
+    if (nz) {
+      const uint32_t below = (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1));
+      const int slot = (cx.head + cx.nrec + (int)below) & (DENSE_RING - 1);
+      const bool fits = k0 == (int64_t)(int32_t)k0 && k1 == (int64_t)(int32_t)k1 && k2 == (int64_t)(int32_t)k2;
+      int4 x, y;
+      x.x = (int32_t)(k0 & DENSE_LMASK), x.y = (int32_t)(k0 >> DENSE_LIMB);
+      x.z = (int32_t)(k1 & DENSE_LMASK), x.w = (int32_t)(k1 >> DENSE_LIMB);
+      y.x = (int32_t)(k2 & DENSE_LMASK), y.y = (int32_t)(k2 >> DENSE_LIMB);
+      y.z = d, y.w = c1 | (c2 << 8) | (c3 << 16) | (fits ? REC_FITS : 0);
+      *(int4 *)&cx.lds->rec[slot][0] = x;
+      *(int4 *)&cx.lds->rec[slot][4] = y;
+    }
+    const int added = __builtin_popcountll(m);
+    if constexpr (S) cx.leaves += (uint32_t)added;
+    cx.nrec += added;
+    wave_sync_lds();
+    if (cx.nrec >= 64) {
+      if (!charge(cx, 1)) return;
+      test_batch(cx, 64, 0);
+    }
+  }
+  // 4. the node's last records, each candidate's points over 64 / 2^logC lanes
+  if (cx.nrec > 0) {
+    if (!charge(cx, 1)) return;
+    int logC = 0;
+    while (logC < 6 && (cx.nrec << (logC + 1)) <= 64) logC++;
+    test_batch(cx, cx.nrec, logC);
+  }
+  wave_sync_lds(); // the next node rewrites the rows
+}
+
+// Range of the next element at depth T (as next_range in enum_device.hpp).
+template <class CX>
+__device__ __forceinline__ void dense_next_range(const CX &cx, int T, int K, int low, int *hi_c, int *lo_c) {
+  if (T + 1 < cx.L) {
+    const uint64_t below = cx.mask & ((1ull << low) - 1);
+    *hi_c = *lo_c = 63 - __builtin_clzll(below);
+    return;
+  }
+  *hi_c = low - 1;
+  *lo_c = K - T - 1;
+  if (T + 1 == cx.L) {
+    *hi_c = min(*hi_c, cx.c_hi);
+    *lo_c = max(*lo_c, cx.c_lo);
+  }
+}
+
+// st holds depth T (T+1 points chosen, lowest `low`), W = K - T >= 3 columns.
+template <int K, int T, class CX>
+struct DLevel {
+  static __device__ __forceinline__ void run(CX &cx, const St<K - T> &st, int low) {
+    constexpr int W = K - T;
+    if constexpr (W == 3) {
+      triple_stage<K>(cx, st, low);
+    } else {
+      int hi_c, lo_c;
+      dense_next_range(cx, T, K, low, &hi_c, &lo_c);
+      for (int c = hi_c; c >= lo_c && step_ok(cx); --c) {
+        int32_t rc[W];
+#pragma unroll
+        for (int i = 0; i < W; i++) rc[i] = rl32(st.s[i], c);
+        int p = -1;
+#pragma unroll
+        for (int i = 0; i < W; i++)
+          if (p < 0 && rc[i] != 0) p = i;
+        if (p < 0) { // affinely dependent on the prefix: D = 0 below
+          if constexpr (CX::stats) cx.pruned++;
+          continue;
+        }
+        int32_t piv = rc[0], rjp = st.s[0];
+#pragma unroll
+        for (int i = 1; i < W; i++)
+          if (p == i) {
+            piv = rc[i];
+            rjp = st.s[i];
+          }
+        const int32_t h1c = rl32(st.H1, c), h0c = rl32(st.H0, c);
+        const Div dv = make_div(st.prev);
+        St<W - 1> ch;
+#pragma unroll
+        for (int i = 0; i < W - 1; i++) {
+          const bool sh = i >= p;
+          const int32_t src = sh ? st.s[i + 1] : st.s[i];
+          const int32_t rcs = sh ? rc[i + 1] : rc[i];
+          ch.s[i] = exdiv32((int64_t)piv * src - (int64_t)rcs * rjp, dv);
+        }
+        const int64_t A = (int64_t)piv * st.H1 - (int64_t)h1c * rjp;
+        const int64_t B = (int64_t)piv * st.H0 - (int64_t)h0c * rjp;
+        const int64_t h = exdiv_split(A, B, dv);
+        ch.H1 = (int32_t)(h >> 31);
+        ch.H0 = (int32_t)((uint32_t)h & LOW31);
+        ch.prev = piv;
+        if constexpr (CX::stats) {
+          cx.inner++;
+          cx.sp_upd += W - 1;
+        }
+        cx.chosen |= 1ull << c;
+        DLevel<K, T + 1, CX>::run(cx, ch, c);
+        cx.chosen &= ~(1ull << c);
+      }
+    }
+  }
+};
+
+template <int K, class CX>
+__device__ __forceinline__ void dense_tile(CX &cx, const SysDesc &sd, const int32_t *__restrict__ pts,
+                                           const int64_t *__restrict__ hts) {
+  const bool valid = cx.j < sd.N;
+  int32_t P[K];
+  int64_t w = 0;
+#pragma unroll
+  for (int i = 0; i < K; i++) P[i] = 0;
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < K; i++) P[i] = pts[sd.pt_off + cx.j * K + i];
+    w = hts[sd.ht_off + cx.j];
+  }
+  const int base = 63 - __builtin_clzll(cx.mask);
+  const int64_t wb = (int64_t)(((uint64_t)(uint32_t)rl32((int32_t)(uint32_t)((uint64_t)w >> 32), base) << 32) |
+                               (uint32_t)rl32((int32_t)(uint32_t)w, base));
+  const int64_t h0 = valid ? w - wb : 0; // padding lanes: zero rows
+  St<K> st;
+#pragma unroll
+  for (int i = 0; i < K; i++) st.s[i] = valid ? P[i] - rl32(P[i], base) : 0;
+  st.H1 = (int32_t)(h0 >> 31);
+  st.H0 = (int32_t)((uint32_t)h0 & LOW31);
+  st.prev = 1;
+  cx.chosen = 1ull << base;
+  DLevel<K, 0, CX>::run(cx, st, base);
+}
+
+template <int KLO, int KHI, int MODE>
+__device__ __forceinline__ void dense_unit(const Tile &tl, const SysDesc &sd, const int32_t *__restrict__ pts,
+                                           const int64_t *__restrict__ hts, SysAcc *__restrict__ acc,
+                                           DevCounters *__restrict__ cnt, const CellSink &sink, DenseLds *lds) {
+  using CX = DCtx<MODE>;
+  constexpr bool S = CX::stats;
+  const int lane = lane_id();
+  CX cx;
+  cx.N = sd.N;
+  cx.k = sd.k;
+  cx.j = lane;
+  cx.mask = tl.mask;
+  cx.L = __builtin_popcountll(tl.mask);
+  cx.c_lo = tl.c_lo;
+  cx.c_hi = tl.c_hi;
+  cx.lds = lds;
+  cx.head = 0;
+  cx.nrec = 0;
+  cx.inner = cx.sp_upd = cx.pruned = cx.nodes = cx.triples = cx.leaves = cx.setups = cx.tests = 0;
+  cx.sink = sink;
+  if (lane == 0) {
+    lds->tally.acc = 0;
+    lds->tally.cells = 0;
+    lds->tally.tie = 0;
+  }
+  {
+    const uint64_t cand = unit_candidates(sd.k, tl.mask, tl.c_lo, tl.c_hi);
+    const uint64_t b = cand * (uint64_t)(sd.k + 3) + 256;
+    cx.left = b > 0x7FFFFFF0ull ? 0x7FFFFFF0 : (int32_t)b;
+  }
+  switch (sd.k) {
+#define BDEG_DCASE(KK)                                     \
+  case KK:                                                 \
+    if constexpr (KK >= KLO && KK <= KHI && KK >= 3)       \
+      dense_tile<KK, CX>(cx, sd, pts, hts);                \
+    break;
+    BDEG_DCASE(3) BDEG_DCASE(4) BDEG_DCASE(5) BDEG_DCASE(6) BDEG_DCASE(7) BDEG_DCASE(8)
+    BDEG_DCASE(9) BDEG_DCASE(10) BDEG_DCASE(11) BDEG_DCASE(12) BDEG_DCASE(13) BDEG_DCASE(14)
+    BDEG_DCASE(15) BDEG_DCASE(16) BDEG_DCASE(17) BDEG_DCASE(18)
+#undef BDEG_DCASE
+    default:
+      break;
+  }
+  wave_sync_lds();
+  const bool abandoned = cx.left <= 0;
+  if (lane == 0 && abandoned) atomicOr(&cnt->error, 1u);
+  if (lane == 0 && !abandoned) {
+    const unsigned long long sum = lds->tally.acc;
+    const uint32_t cells = lds->tally.cells, tie = lds->tally.tie;
+    if (sum | cells | tie) {
+      SysAcc *a = &acc[tl.sys];
+      const unsigned long long old = atomicAdd((unsigned long long *)&a->lo, sum);
+      if (old + sum < old) atomicAdd((unsigned long long *)&a->hi, 1ull);
+      atomicAdd((unsigned long long *)&a->cells, (unsigned long long)cells);
+      if (tie) atomicOr(&a->tie, 1u);
+    }
+    if constexpr (S) {
+      const unsigned long long n = (unsigned long long)sd.N, t = (unsigned long long)(sd.N - sd.k - 1);
+      atomicAdd((unsigned long long *)&cnt->inner, (unsigned long long)cx.inner);
+      atomicAdd((unsigned long long *)&cnt->sp_upd, (unsigned long long)cx.sp_upd);
+      atomicAdd((unsigned long long *)&cnt->pruned, (unsigned long long)cx.pruned);
+      // (no ridges in this schedule: setup passes and test batches take the
+      // ridge- and leaf-step counters)
+      atomicAdd((unsigned long long *)&cnt->leaves, (unsigned long long)cx.leaves);
+      atomicAdd((unsigned long long *)&cnt->rsteps, (unsigned long long)cx.setups);
+      atomicAdd((unsigned long long *)&cnt->lsteps, (unsigned long long)cx.tests);
+      atomicAdd((unsigned long long *)&cnt->triples, (unsigned long long)cx.triples);
+      atomicAdd((unsigned long long *)&cnt->dunits, 1ull);
+      atomicAdd((unsigned long long *)&cnt->tiles, 1ull);
+      atomicAdd((unsigned long long *)&cnt->w_inner, n * cx.inner);
+      atomicAdd((unsigned long long *)&cnt->w_spatial, n * cx.sp_upd);
+      atomicAdd((unsigned long long *)&cnt->w_leaves, t * cx.leaves);
+    }
+  }
+}
+
+// Waves per SIMD the dense kernel is compiled for: the depth-first states
+// above the triple stage grow with k (about (k^2 + 7k) / 2 registers), the
+// triple stage adds a fixed working set; six waves is also the LDS limit
+// (24 KiB per block of four).
+constexpr int dense_waves(int k) { return k <= 6 ? 6 : k <= 10 ? 4 : k <= 13 ? 3 : 2; }
+
+template <int KLO, int KHI, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dense_waves(KHI))))
+dense_kernel(const SysDesc *__restrict__ sys, const int32_t *__restrict__ pts, const int64_t *__restrict__ hts,
+             const Tile *__restrict__ tiles, uint32_t n_tiles, SysAcc *__restrict__ acc,
+             DevCounters *__restrict__ cnt, CellSink sink, const uint32_t *__restrict__ rerun) {
+  const int lane = lane_id();
+  __shared__ DenseLds lds_all[4]; // one per wavefront of the block (at most 256 threads)
+  DenseLds *lds = &lds_all[threadIdx.x >> 6];
+  if (rerun && rerun[0] == 0) return;
+  for (;;) {
+    // every lane joins the claim; lane 0's result is read by index (no
+    // lane-dependent branch around the loop's exit test)
+    const uint32_t claim = atomicAdd(&cnt->next_tile, lane == 0 ? 1u : 0u);
+    const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int32_t)claim, 0);
+    if (t >= n_tiles) break;
+    const Tile tl = tiles[t];
+    if (rerun && rerun[1 + tl.sys] == 0) continue;
+    const SysDesc sd = sys[tl.sys];
+    dense_unit<KLO, KHI, MODE>(tl, sd, pts, hts, acc, cnt, sink, lds);
+  }
+}
+
+} // namespace dev
+} // namespace bdeg
+
+// Instantiation helper: one translation unit per k range defines
+// bdeg::enum_fn_<klo>_<khi>(mode, variant) for the three kernel variants
+// (0: lane groups read per system, 1: one point group per wavefront, 2: the
+// lane-dense kernel, k >= 3).  The emitting mode exists for single-k kernels
+// only.
+namespace bdeg {
+namespace dev {
+template <int KLO, int KHI>
+EnumFn pick_dense(int mode) {
+  if constexpr (KHI < 3) {
+    return nullptr;
+  } else {
+    if (mode == MODE_STATS) return dense_kernel<KLO, KHI, MODE_STATS>;
+    if (mode == MODE_EMIT) {
+      if constexpr (KLO == KHI) return dense_kernel<KLO, KHI, MODE_EMIT>;
+      else return nullptr;
+    }
+    return dense_kernel<KLO, KHI, MODE_PLAIN>;
+  }
+}
+} // namespace dev
+} // namespace bdeg
+
+#define BDEG_ENUM_INSTANCES(KLO, KHI)                                                         \
+  namespace bdeg {                                                                            \
+  EnumFn enum_fn_##KLO##_##KHI(int mode, int variant) {                                       \
+    return variant == 2 ? dev::pick_dense<KLO, KHI>(mode) : dev::pick_kernel<KLO, KHI>(mode, variant == 1); \
+  }                                                                                           \
+  }

@@ -725,7 +725,3 @@ EnumFn pick_kernel(int mode, bool single) {
 } // namespace dev
 } // namespace bdeg
 
-#define BDEG_ENUM_INSTANCES(KLO, KHI)                                                                   \
-  namespace bdeg {                                                                                      \
-  EnumFn enum_fn_##KLO##_##KHI(int mode, bool single) { return dev::pick_kernel<KLO, KHI>(mode, single); } \
-  }

@@ -31,6 +31,7 @@ __device__ __forceinline__ void clear_counters(DevCounters *cnt) {
   cnt->ridges = cnt->inner = cnt->sp_upd = cnt->pruned = cnt->leaves = cnt->tiles = 0;
   cnt->rsteps = cnt->lsteps = cnt->lempty = 0;
   cnt->w_inner = cnt->w_spatial = cnt->w_ridges = cnt->w_leaves = 0;
+  cnt->triples = cnt->dunits = 0;
   cnt->next_tile = 0;
   cnt->error = 0;
 }
@@ -124,57 +125,58 @@ int launch_clear_list(void *stream, SysAcc *d_acc, const int32_t *d_list, int n)
 }
 
 // per-k-range instantiations (kernels_k*.hip)
-EnumFn enum_fn_1_1(int, bool);
-EnumFn enum_fn_2_2(int, bool);
-EnumFn enum_fn_3_3(int, bool);
-EnumFn enum_fn_4_4(int, bool);
-EnumFn enum_fn_5_5(int, bool);
-EnumFn enum_fn_6_6(int, bool);
-EnumFn enum_fn_7_7(int, bool);
-EnumFn enum_fn_8_8(int, bool);
-EnumFn enum_fn_9_9(int, bool);
-EnumFn enum_fn_10_10(int, bool);
-EnumFn enum_fn_11_11(int, bool);
-EnumFn enum_fn_12_12(int, bool);
-EnumFn enum_fn_13_13(int, bool);
-EnumFn enum_fn_14_14(int, bool);
-EnumFn enum_fn_15_15(int, bool);
-EnumFn enum_fn_16_16(int, bool);
-EnumFn enum_fn_17_17(int, bool);
-EnumFn enum_fn_18_18(int, bool);
-EnumFn enum_fn_1_7(int, bool);
-EnumFn enum_fn_1_12(int, bool);
+EnumFn enum_fn_1_1(int, int);
+EnumFn enum_fn_2_2(int, int);
+EnumFn enum_fn_3_3(int, int);
+EnumFn enum_fn_4_4(int, int);
+EnumFn enum_fn_5_5(int, int);
+EnumFn enum_fn_6_6(int, int);
+EnumFn enum_fn_7_7(int, int);
+EnumFn enum_fn_8_8(int, int);
+EnumFn enum_fn_9_9(int, int);
+EnumFn enum_fn_10_10(int, int);
+EnumFn enum_fn_11_11(int, int);
+EnumFn enum_fn_12_12(int, int);
+EnumFn enum_fn_13_13(int, int);
+EnumFn enum_fn_14_14(int, int);
+EnumFn enum_fn_15_15(int, int);
+EnumFn enum_fn_16_16(int, int);
+EnumFn enum_fn_17_17(int, int);
+EnumFn enum_fn_18_18(int, int);
+EnumFn enum_fn_1_7(int, int);
+EnumFn enum_fn_1_12(int, int);
 
 // Single-k kernels (exact register budget) and mixed-k kernels for batches,
-// each in a one-group-per-wavefront variant (`single`, N > 32) and a variant
-// that reads the group count per system; `mode` selects plain, counting
-// (MODE_STATS) or cell-listing (MODE_EMIT, single-k only).
-static EnumFn enum_fn(int klo, int khi, int mode, bool single) {
+// each in three variants: lane groups read per system (0), one point group
+// per wavefront (1, N > 32), and the lane-dense kernel (2, k >= 3); `mode`
+// selects plain, counting (MODE_STATS) or cell-listing (MODE_EMIT, single-k
+// only).
+static EnumFn enum_fn(int klo, int khi, int mode, int variant) {
   if (klo == khi) {
     switch (khi) {
-      case 1: return enum_fn_1_1(mode, single);
-      case 2: return enum_fn_2_2(mode, single);
-      case 3: return enum_fn_3_3(mode, single);
-      case 4: return enum_fn_4_4(mode, single);
-      case 5: return enum_fn_5_5(mode, single);
-      case 6: return enum_fn_6_6(mode, single);
-      case 7: return enum_fn_7_7(mode, single);
-      case 8: return enum_fn_8_8(mode, single);
-      case 9: return enum_fn_9_9(mode, single);
-      case 10: return enum_fn_10_10(mode, single);
-      case 11: return enum_fn_11_11(mode, single);
-      case 12: return enum_fn_12_12(mode, single);
-      case 13: return enum_fn_13_13(mode, single);
-      case 14: return enum_fn_14_14(mode, single);
-      case 15: return enum_fn_15_15(mode, single);
-      case 16: return enum_fn_16_16(mode, single);
-      case 17: return enum_fn_17_17(mode, single);
-      case 18: return enum_fn_18_18(mode, single);
+      case 1: return enum_fn_1_1(mode, variant);
+      case 2: return enum_fn_2_2(mode, variant);
+      case 3: return enum_fn_3_3(mode, variant);
+      case 4: return enum_fn_4_4(mode, variant);
+      case 5: return enum_fn_5_5(mode, variant);
+      case 6: return enum_fn_6_6(mode, variant);
+      case 7: return enum_fn_7_7(mode, variant);
+      case 8: return enum_fn_8_8(mode, variant);
+      case 9: return enum_fn_9_9(mode, variant);
+      case 10: return enum_fn_10_10(mode, variant);
+      case 11: return enum_fn_11_11(mode, variant);
+      case 12: return enum_fn_12_12(mode, variant);
+      case 13: return enum_fn_13_13(mode, variant);
+      case 14: return enum_fn_14_14(mode, variant);
+      case 15: return enum_fn_15_15(mode, variant);
+      case 16: return enum_fn_16_16(mode, variant);
+      case 17: return enum_fn_17_17(mode, variant);
+      case 18: return enum_fn_18_18(mode, variant);
       default: return nullptr;
     }
   }
-  if (khi <= 7) return enum_fn_1_7(mode, single);
-  if (khi <= 12) return enum_fn_1_12(mode, single);
+  if (khi <= 7) return enum_fn_1_7(mode, variant);
+  if (khi <= 12) return enum_fn_1_12(mode, variant);
   return nullptr;
 }
 
@@ -185,8 +187,10 @@ int device_cu_count() {
   return n;
 }
 
-int max_enum_blocks(int klo, int khi, int waves_per_block, bool single) {
-  EnumFn f = enum_fn(klo, khi, MODE_PLAIN, single);
+static int variant_of(bool single, bool dense) { return dense ? 2 : single ? 1 : 0; }
+
+int max_enum_blocks(int klo, int khi, int waves_per_block, bool single, bool dense) {
+  EnumFn f = enum_fn(klo, khi, MODE_PLAIN, variant_of(single, dense));
   if (!f) return 0;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)f, waves_per_block * 64, 0) != hipSuccess)
@@ -197,13 +201,13 @@ int max_enum_blocks(int klo, int khi, int waves_per_block, bool single) {
 int launch_enumerate(void *stream, const SysDesc *d_sys, const int32_t *d_pts, const int64_t *d_heights,
                      const Tile *d_tiles, uint32_t n_tiles, SysAcc *d_acc, DevCounters *d_cnt, int klo, int khi,
                      LaunchShape shape) {
-  EnumFn f = enum_fn(klo, khi, shape.mode, shape.single);
+  EnumFn f = enum_fn(klo, khi, shape.mode, variant_of(shape.single, shape.dense));
   if (shape.mode == MODE_EMIT && (!shape.sink.count || (shape.sink.cap > 0 && !shape.sink.masks))) return BDEG_E_ARG;
   if (!f) return BDEG_E_TOO_LARGE;
   if (n_tiles == 0) return BDEG_OK;
   int blocks = shape.blocks;
   const int wpb = shape.waves_per_block > 0 ? shape.waves_per_block : 4;
-  if (blocks <= 0) blocks = max_enum_blocks(klo, khi, wpb, shape.single);
+  if (blocks <= 0) blocks = max_enum_blocks(klo, khi, wpb, shape.single, shape.dense);
   if (blocks <= 0) return BDEG_E_DEVICE;
   const uint64_t need = ((uint64_t)n_tiles + wpb - 1) / wpb;
   if ((uint64_t)blocks > need) blocks = (int)need;

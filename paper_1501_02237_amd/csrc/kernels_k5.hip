@@ -1,4 +1,4 @@
 // Enumeration kernels for k = 5: both lane-group variants, plain, counting and
 // cell-listing modes (instantiated from enum_device.hpp).
-#include "enum_device.hpp"
+#include "enum_dense.hpp"
 BDEG_ENUM_INSTANCES(5, 5)

@@ -1,4 +1,4 @@
 // Enumeration kernels for batches mixing k = 1..12.
-#include "enum_device.hpp"
+#include "enum_dense.hpp"
 
 BDEG_ENUM_INSTANCES(1, 12)

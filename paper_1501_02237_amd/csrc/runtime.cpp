@@ -4,10 +4,24 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <atomic>
 
 namespace bdeg {
 
 static Device g_device;
+static std::atomic<int> g_schedule{BDEG_SCHED_AUTO};
+
+int schedule_mode() { return g_schedule.load(std::memory_order_relaxed); }
+int schedule_set(int s) {
+  if (s != BDEG_SCHED_AUTO && s != BDEG_SCHED_POINTS) return BDEG_E_ARG;
+  g_schedule.store(s, std::memory_order_relaxed);
+  return BDEG_OK;
+}
+
+bool dense_ok(const int32_t *pts, int N, int k, uint64_t height_span) {
+  if (k < 3 || schedule_mode() != BDEG_SCHED_AUTO) return false;
+  return device_bounds_ok(pts, N, k, height_span, 30, 59);
+}
 static std::once_flag g_once;
 static int g_status = BDEG_E_DEVICE;
 static int g_requested = -1;
@@ -92,7 +106,7 @@ void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t ma
     d.lift_key = lift_key(h.seed, 0u, h.attempt);
     d.seed = h.seed;
     d.sys_index = 0;
-    d.pad = 0;
+    d.flags = dense_ok(h.pts.data(), h.N, h.k, (1ull << h.lift_bits) - 1) ? SYS_DENSE : 0;
     job.sys.push_back(d);
     job.pts.insert(job.pts.end(), h.pts.begin(), h.pts.end());
     ht += h.N;
@@ -111,9 +125,13 @@ void job_order_units(Job &job, std::vector<TileC> &tc) {
     const int k = job.sys[t.t.sys].k;
     return (job.kmin != job.kmax && k <= MIXED_K_MAX) ? 0 : k;
   };
+  // kernel variant: 0 lane groups, 1 one point group per wavefront, 2 lane-dense
+  auto variant = [&](const TileC &t) {
+    const SysDesc &d = job.sys[t.t.sys];
+    return (d.flags & SYS_DENSE) ? 2 : d.npad_log2 == 6 ? 1 : 0;
+  };
   std::stable_sort(tc.begin(), tc.end(), [&](const TileC &a, const TileC &b) {
-    // one point group per wavefront (64 lanes per group) runs in its own variant
-    const bool ga = job.sys[a.t.sys].npad_log2 == 6, gb = job.sys[b.t.sys].npad_log2 == 6;
+    const int ga = variant(a), gb = variant(b);
     if (ga != gb) return ga < gb;
     const int ka = kclass(a), kb = kclass(b);
     if (ka != kb) return ka < kb;
@@ -123,11 +141,14 @@ void job_order_units(Job &job, std::vector<TileC> &tc) {
   job.granges.clear();
   for (size_t i = 0; i < tc.size(); i++) {
     job.tiles[i] = tc[i].t;
-    const bool g = job.sys[tc[i].t.sys].npad_log2 == 6;
+    const int v = variant(tc[i]);
+    const bool g = v == 1, dn = v == 2;
     const int kc = kclass(tc[i]);
-    if (job.granges.empty() || job.granges.back().single != g || job.granges.back().kclass != kc) {
+    if (job.granges.empty() || job.granges.back().single != g || job.granges.back().dense != dn ||
+        job.granges.back().kclass != kc) {
       Job::VariantRange r;
       r.single = g;
+      r.dense = dn;
       r.kclass = kc;
       r.klo = kc != 0 ? kc : job.kmin;
       r.khi = kc != 0 ? kc : std::min(job.kmax, MIXED_K_MAX);
@@ -205,6 +226,7 @@ int job_launch_enum(Job &job, hipStream_t stream, int round) {
     const Job::VariantRange &r = job.granges[i];
     LaunchShape shape = job.shape;
     shape.single = r.single;
+    shape.dense = r.dense;
     shape.rerun = round ? job.d_rerun + (size_t)(round - 1) * (job.sys.size() + 1) : nullptr;
     int rc = launch_enumerate(stream, job.d_sys, job.d_pts, job.d_hts, job.d_tiles + r.start, r.count, job.d_acc,
                               job.d_cnt + (size_t)round * MAX_RANGES + i, r.klo, r.khi, shape);
@@ -246,6 +268,8 @@ int job_collect(Job &job, hipStream_t stream, std::vector<SysAcc> &acc, DevCount
     sum.w_spatial += b.w_spatial;
     sum.w_ridges += b.w_ridges;
     sum.w_leaves += b.w_leaves;
+    sum.triples += b.triples;
+    sum.dunits += b.dunits;
     sum.error |= b.error;
   }
   if (cnt) *cnt = sum;

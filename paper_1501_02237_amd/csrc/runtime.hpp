@@ -52,6 +52,7 @@ struct Job {
   // kernels); one launch, with its own counter block, per range present
   struct VariantRange {
     bool single;
+    bool dense; // the lane-dense kernel (SYS_DENSE systems)
     int kclass; // 0: mixed-k kernel; else the single k
     int klo, khi;
     uint32_t start, count;
@@ -92,11 +93,15 @@ void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t ma
 // Order units by (kernel variant, decreasing cost) and record the variant ranges.
 void job_order_units(Job &job, std::vector<TileC> &tc);
 // index of a kernel variant among the per-(k, variant) counter blocks of the serving engine
-inline int group_slot(bool single) { return single ? 1 : 0; }
-constexpr int GROUP_SLOTS = 2;
+inline int group_slot(bool single, bool dense) { return dense ? 2 : single ? 1 : 0; }
+constexpr int GROUP_SLOTS = 3;
+// Enumeration schedule of the process (bdeg_set_schedule): BDEG_SCHED_AUTO
+// runs certified systems with k >= 3 in the lane-dense kernel.
+int schedule_mode();
+int schedule_set(int schedule);
 // deepest k of the mixed-k kernels; launch ranges of a job (each has a counter block)
 constexpr int MIXED_K_MAX = 12;
-constexpr int MAX_RANGES = 2 * (1 + BDEG_MAX_K - MIXED_K_MAX);
+constexpr int MAX_RANGES = 3 * (1 + BDEG_MAX_K - MIXED_K_MAX);
 // redraw rounds inside one replayable device pass (a prepared batch): after
 // the first enumeration, each round redraws the liftings of the tied systems
 // and enumerates their units again; ties left after the last round are

@@ -74,6 +74,7 @@ struct Request {
   bdeg_result res{};
   HostSys hs;
   bool need_dev = false;
+  bool dense = false; // runs in the lane-dense kernel
   int state = 0; // 0 queued, 1 waiting admission, 2 active, 3 done, 4 taken
   int slot = -1;
   std::vector<Tile> tiles;
@@ -207,7 +208,8 @@ void bdeg_server::start_attempt(Request *r) {
   d.lift_key = lift_key(r->hs.seed, 0u, r->hs.attempt); // the single-system stream
   d.seed = r->hs.seed;
   d.sys_index = 0;
-  d.pad = 0;
+  r->dense = dense_ok(r->hs.pts.data(), d.N, d.k, (1ull << d.lift_bits) - 1);
+  d.flags = r->dense ? SYS_DENSE : 0;
   (void)hipMemcpyAsync(d_sys + r->slot, &d, sizeof(SysDesc), hipMemcpyHostToDevice, stream);
   // units are taken round-robin across requests in small steps, so their
   // order within a request does not matter: no sort
@@ -321,7 +323,7 @@ void bdeg_server::run() {
       for (Request *r : active) {
         if (r->next >= r->tiles.size() || nt >= STEP_TILES_MAX) continue;
         const Tile &t = r->tiles[r->next++];
-        byk[r->hs.k * GROUP_SLOTS + group_slot(single_group(r->hs.N))].push_back(t);
+        byk[r->hs.k * GROUP_SLOTS + group_slot(single_group(r->hs.N), r->dense)].push_back(t);
         nt++;
         uint64_t s0, e0;
         tile_interval(t, r->hs.k, &s0, &e0);
@@ -347,7 +349,8 @@ void bdeg_server::run() {
         for (int b = 0; b < NB && !rc; b++) {
           if (byk[b].empty()) continue;
           LaunchShape shape;
-          shape.single = b % GROUP_SLOTS == group_slot(true);
+          shape.single = b % GROUP_SLOTS == group_slot(true, false);
+          shape.dense = b % GROUP_SLOTS == group_slot(false, true);
           rc = launch_enumerate(stream, d_sys, d_pts, d_hts, d_tiles + start[b], (uint32_t)byk[b].size(), d_acc,
                                 d_cnt + b, b / GROUP_SLOTS, b / GROUP_SLOTS, shape);
         }
@@ -365,7 +368,8 @@ void bdeg_server::run() {
           const int b = k * GROUP_SLOTS + gs;
           if (byk[b].empty()) continue;
           LaunchShape shape;
-          shape.single = gs == group_slot(true);
+          shape.single = gs == group_slot(true, false);
+          shape.dense = gs == group_slot(false, true);
           rc = launch_enumerate(kstream[k], d_sys, d_pts, d_hts, d_tiles + start[b], (uint32_t)byk[b].size(), d_acc,
                                 d_cnt + b, k, k, shape);
         }
