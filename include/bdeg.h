@@ -104,9 +104,13 @@ typedef struct {
   uint64_t point_spatial;     /* sum of N * spatial_updates */
   uint64_t point_ridges;      /* sum of N * ridges */
   uint64_t leaf_points;       /* sum of (N - k - 1) * leaves: points tested by the leaf tests */
-  /* lane-dense schedule (BDEG_SCHED_AUTO): it creates no ridges; its leaves
-     are the candidates with D != 0 it tested, ridge_steps its setup passes
-     and leaf_steps its test batches */
+  /* lane-dense schedule (BDEG_SCHED_AUTO): it creates no ridges; there
+     `ridges` counts its nodes with three spatial columns left, `leaves` the
+     candidates with D != 0 it tested, ridge_steps its setup passes,
+     leaf_steps its test batches and empty_steps the candidates no point
+     rejected in the batch test, decided exactly one by one (the cells, the
+     ties and the rare candidates whose points below all lie in the test's
+     rounding band) */
   uint64_t triples;           /* candidates set up at nodes with three spatial columns left (any D) */
   uint64_t dense_units;       /* work units run by the lane-dense kernel */
   float kernel_ms;            /* device time of the enumeration kernel, HIP events */
@@ -195,10 +199,12 @@ int bdeg_batch_destroy(bdeg_batch *b);
  * buckets of equal k and equal smallest lane-group width (8, 16, 32 or 64
  * lanes per point group for N <= 8, 16, 32, 64 points).  For each bucket the
  * bucket's systems are enumerated alone under every schedule of a small grid
- * (lane-group width: the smallest or the next larger one, 64 lanes meaning
- * one group per wavefront in its own kernel variant; work-unit size cap:
- * 128 .. 8192 candidates) and under the default schedule, each timed by HIP
- * events (median of `reps` passes after a warm-up).  Every schedule must give
+ * (the kernel: lanes as points -- a point per lane, at the smallest or the
+ * next larger lane-group width, 64 lanes meaning one group per wavefront in
+ * its own kernel variant -- or lane-dense, a candidate per lane, for the
+ * systems it is certified for; work-unit size cap: 128 .. 8192 candidates)
+ * and under the default schedule, each timed by HIP events (median of `reps`
+ * passes after a warm-up).  Every schedule must give
  * exactly the default's sums for every system (the same liftings and
  * candidates), else BDEG_E_STATE and nothing is written.  The fastest
  * schedule per bucket is written to the JSON table `table_path` (entries of

@@ -632,25 +632,31 @@ int bdeg_batch_tune(bdeg_batch *b, const char *table_path, int32_t reps) {
       if (rc) return rc;
       BucketSchedule pick;
       pick.ms = ms_best;
-      for (int w = g; w <= std::min(6, g + 1); w++)
-        for (uint64_t cost : COSTS) {
-          ScheduleTable one;
-          one.e[k][g].npad_log2 = w;
-          one.e[k][g].unit_cost = cost;
-          one.any = true;
-          float ms = 0;
-          rc = time_schedule(D, sys, &one, reps, &ms, &sums);
-          if (rc) return rc;
-          for (size_t i = 0; i < ref.size(); i++)
-            if (sums[i].lo != ref[i].lo || sums[i].hi != ref[i].hi || sums[i].cells != ref[i].cells ||
-                sums[i].tie != ref[i].tie)
-              return BDEG_E_STATE; // a schedule changed a result: never persist it
-          if (ms < pick.ms) {
-            pick.ms = ms;
-            pick.npad_log2 = w;
-            pick.unit_cost = cost;
+      // the kernel: lanes as points at the smallest or the next lane-group
+      // width, or lane-dense (for the systems it is certified for; the group
+      // width does not apply); each at every unit size
+      for (int dense = 0; dense <= 1; dense++)
+        for (int w = g; w <= (dense ? g : std::min(6, g + 1)); w++)
+          for (uint64_t cost : COSTS) {
+            ScheduleTable one;
+            one.e[k][g].dense = dense;
+            one.e[k][g].npad_log2 = w;
+            one.e[k][g].unit_cost = cost;
+            one.any = true;
+            float ms = 0;
+            rc = time_schedule(D, sys, &one, reps, &ms, &sums);
+            if (rc) return rc;
+            for (size_t i = 0; i < ref.size(); i++)
+              if (sums[i].lo != ref[i].lo || sums[i].hi != ref[i].hi || sums[i].cells != ref[i].cells ||
+                  sums[i].tie != ref[i].tie)
+                return BDEG_E_STATE; // a schedule changed a result: never persist it
+            if (ms < pick.ms) {
+              pick.ms = ms;
+              pick.dense = dense;
+              pick.npad_log2 = w;
+              pick.unit_cost = cost;
+            }
           }
-        }
       pick.systems = (int)sys.size();
       if (pick.npad_log2 == 0) { // the default won: record it explicitly
         pick.npad_log2 = g;

@@ -22,24 +22,29 @@
 //     (point j's height over the candidate's hyperplane, times D) and prev is
 //     the node's last pivot.  A candidate is a lower facet exactly when
 //     sign(D) sign(prev) u_j > 0 for every point j off the candidate.
-//   * Triples with D != 0 are compacted into a ring of records in LDS; a test
-//     batch takes 64 records and loops over the points, every lane testing
-//     its own candidate against point j (row j is one broadcast LDS read), so
-//     all 64 lanes do the same useful work and consecutive points are
-//     independent chains.  A node with fewer than 64 candidates left splits
-//     each candidate's points over C = 2, 4, ... lanes.
-//   * The batch test is a filter on the high limbs (four multiply-adds per
-//     point), exact in what it rejects.  The rare survivors are decided
-//     exactly with lanes as points: a point strictly below rejects, else the
-//     zero count tells a lower facet (exactly the k + 1 vertices vanish) from
-//     a tie.
+//   * Triples with D != 0 go into a ring of records in LDS; a test batch
+//     takes 64 records and loops over the points, every lane testing its own
+//     candidate against point j (row j is one broadcast LDS read), so all 64
+//     lanes do the same useful work and consecutive points are independent
+//     chains.
+//   * The two most recent nodes keep their rows in two LDS tables, so a setup
+//     pass or a test batch may hold candidates of both: passes and batches
+//     stay full although a node has only a few dozen candidates.  The
+//     pipeline also runs on across the work units of one system; only a
+//     change of system, or the end, drains it (a last batch of fewer than 64
+//     records splits each candidate's points over several lanes).
+//   * The rare candidates that no point rejects are decided exactly with
+//     lanes as points: the zero count tells a lower facet (exactly the k + 1
+//     vertices vanish) from a tie.
 //
 // Widths (certified on the host for these systems: spatial minors < 2^30,
-// height minors < 2^59): heights and height minors are split as
-// x = xh 2^29 + xl with 0 <= xl < 2^29, so every product is a signed
-// 32 x 32 -> 64 multiply-add; the low limbs of u_j sum to less than 2^61 and
-// the high limbs to less than 2^62.  u_j < 0 exactly when its high part
-// (with the low part's carry) is negative.
+// height minors < 2^59): when a node's heights and a record's coefficients
+// fit int32, u_j is four 32 x 32 -> 64 products (each below 2^61) summed in
+// int64; otherwise heights and height minors are split as x = xh 2^29 + xl
+// with 0 <= xl < 2^29, so every product is still a 32 x 32 -> 64
+// multiply-add, the low limbs sum below 2^61 and the high limbs below 2^62,
+// and u_j < 0 exactly when its high part (with the low part's carry) is
+// negative.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -54,11 +59,24 @@ constexpr int DENSE_LIMB = 29;
 constexpr int64_t DENSE_LMASK = (1ll << DENSE_LIMB) - 1;
 constexpr int DENSE_RING = 128; // candidate records per wavefront (a power of two >= 2 * 64)
 
-// Per-wavefront LDS: the current node's point rows and the record ring.
+// Per-wavefront LDS: the point rows of the two most recent nodes and the
+// record ring.
 struct alignas(16) DenseLds {
-  alignas(16) int32_t rows[64][8];        // s0, s1, s2, h (low word), hh, hl; two unused words keep rows 32-byte aligned
-  alignas(16) int32_t rec[DENSE_RING][8]; // kl0, kh0, kl1, kh1, kl2, kh2, d, vertices and REC_FITS
+  alignas(16) int32_t rows[2][64][8];     // s0, s1, s2, h (its low word), hh, hl; two unused words keep rows 32-byte aligned
+  alignas(16) int32_t rec[DENSE_RING][8]; // kl0, kh0, kl1, kh1, kl2, kh2, d, vertices | REC_FITS | table
   Tally tally;
+};
+
+// One node held in a row table (wave-uniform values).
+struct NodeInfo {
+  int t;               // its row table (0 or 1)
+  uint64_t chosen;     // its chosen points (vertices shared by its candidates)
+  uint64_t inv;        // the 2-adic inverse of its pivot (sign folded in)
+  uint32_t e;          // the pivot's 2-adic valuation
+  uint32_t r_cur, r_hi; // its triples still to set up: colex ranks [r_cur, r_hi)
+  uint32_t recs;       // its records in the ring
+  bool prevneg;        // pivot < 0
+  bool rows_fit;       // every height of the node fits int32
 };
 
 template <int MODE>
@@ -69,12 +87,15 @@ struct DCtx {
   uint64_t mask;   // work unit prefix
   int L;           // prefix length
   int c_lo, c_hi;  // sibling run at the first free level
-  uint64_t chosen; // chosen points of the current node
+  uint64_t chosen; // chosen points of the current depth-first node
   DenseLds *lds;
+  // The two most recent nodes, older and newer (each in its own row
+  // table).  A setup pass takes the older node's triples first, then the
+  // newer's; the record ring is in the same order.
+  NodeInfo old, neu;
   int head, nrec;  // record ring: first record and count (wave-uniform)
-  bool rows_fit;   // every height of the current node fits int32
   int32_t left;    // watchdog budget (as in enum_device.hpp)
-  uint32_t inner, sp_upd, pruned, nodes, triples, leaves, setups, tests;
+  uint32_t inner, sp_upd, pruned, nodes, triples, leaves, setups, tests, wide;
   CellSink sink;
 };
 
@@ -124,12 +145,13 @@ __device__ __forceinline__ void acc_limbs(int64_t &Hi, int64_t &Lo, int32_t a, i
   Lo += (int64_t)a * (int32_t)(M & DENSE_LMASK);
 }
 
-// A candidate record: its coefficients k0, k1, k2 split at bit 29
-// (k = kh 2^29 + kl, 0 <= kl < 2^29) as kl0, kh0, kl1, kh1, kl2, kh2, then d,
-// then the vertices c1 | c2 << 8 | c3 << 16, plus REC_FITS when every
-// |k_a| < 2^31.  A node row: s0, s1, s2, h (its low word: the height itself
-// when it fits int32), hh, hl.
+// A candidate record: its coefficients split at bit 29 (k = kh 2^29 + kl,
+// 0 <= kl < 2^29) as kl0, kh0, kl1, kh1, kl2, kh2, then d, then
+// c1 | c2 << 8 | c3 << 16, REC_FITS when every |k_a| < 2^31, and its node
+// table at REC_TABLE_BIT.
 constexpr int REC_FITS = 1 << 24;
+constexpr int REC_TABLE_BIT = 25;
+__device__ __forceinline__ int rec_table(const int32_t *rc) { return (rc[7] >> REC_TABLE_BIT) & 1; }
 
 // u_j = k0 s0 + k1 s1 + k2 s2 + d h exactly, as (hi, lo) with
 // u = 2^29 hi + (lo mod 2^29): every product is a 32 x 32 -> 64 multiply-add
@@ -151,9 +173,9 @@ __device__ __forceinline__ UVal u_exact(const int32_t *rc, int32_t s0, int32_t s
 // lanes as points: a lower facet when exactly its k + 1 vertices vanish, a
 // tie otherwise.
 template <class CX>
-__device__ __forceinline__ void decide_exact(CX &cx, const int32_t *rc) {
+__device__ __forceinline__ void decide_exact(CX &cx, const int32_t *rc, int t) {
   const int lane = lane_id();
-  const int32_t *row = cx.lds->rows[lane];
+  const int32_t *row = cx.lds->rows[t][lane];
   const UVal u = u_exact(rc, row[0], row[1], row[2], row[4], row[5]);
   const bool on = u.hi == 0 && (u.lo & DENSE_LMASK) == 0;
   const uint64_t zero = ballot(on && lane < cx.N);
@@ -161,7 +183,7 @@ __device__ __forceinline__ void decide_exact(CX &cx, const int32_t *rc) {
   if (below) return; // (the batch test is exact: cannot happen)
   const int vtx = rc[7];
   const int c1 = vtx & 255, c2 = (vtx >> 8) & 255, c3 = (vtx >> 16) & 255;
-  const uint64_t verts = cx.chosen | (1ull << c1) | (1ull << c2) | (1ull << c3);
+  const uint64_t verts = (t == cx.old.t ? cx.old.chosen : cx.neu.chosen) | (1ull << c1) | (1ull << c2) | (1ull << c3);
   if (zero != verts) {
     if (lane == 0) cx.lds->tally.tie = 1;
     return;
@@ -189,11 +211,15 @@ __device__ __forceinline__ void test_batch(CX &cx, int n, int logC) {
     rc[0] = a.x, rc[1] = a.y, rc[2] = a.z, rc[3] = a.w, rc[4] = b.x, rc[5] = b.y, rc[6] = b.z, rc[7] = b.w;
   }
   // Exact test.  When the node's heights and every record's coefficients
-  // fit int32 (the common case), u_j is four products of 32-bit values,
-  // each below 2^61 in magnitude, summed exactly in int64; otherwise the
-  // two-limb form.  A candidate with some u_j < 0 is rejected.
+  // fit int32 (the common case for 20-bit liftings), u_j is four products of
+  // 32-bit values, each below 2^61 in magnitude, summed exactly in int64;
+  // otherwise the split-limb form.  A candidate with some u_j < 0 is
+  // rejected; one that no point rejects is decided exactly below.
   const int iters = (cx.N + (1 << logC) - 1) >> logC; // rows past N are zero rows
-  const bool narrow = cx.rows_fit && ballot(valid && !(rc[7] & REC_FITS)) == 0;
+  const int t = rec_table(rc);
+  const bool tfit = t == cx.old.t ? cx.old.rows_fit : cx.neu.rows_fit;
+  const bool narrow = ballot(valid && !((rc[7] & REC_FITS) && tfit)) == 0;
+  const int32_t(*rows)[8] = cx.lds->rows[t];
   int32_t neg = 0;
   if (narrow) {
     // each |k_a| < 2^31: the 32-bit values themselves (wrapping arithmetic
@@ -204,7 +230,7 @@ __device__ __forceinline__ void test_batch(CX &cx, int n, int logC) {
 #pragma unroll 4
     for (int it = 0; it < iters; it++) {
       const int j = q + (it << logC); // < 64: 2^logC divides 64 and N <= 64
-      const int4 r = *(const int4 *)&cx.lds->rows[j][0];
+      const int4 r = *(const int4 *)&rows[j][0];
       const int64_t u = (int64_t)r.x * k0 + (int64_t)r.y * k1 + (int64_t)r.z * k2 + (int64_t)r.w * rc[6];
       neg |= (int32_t)((uint64_t)u >> 32);
     }
@@ -212,8 +238,8 @@ __device__ __forceinline__ void test_batch(CX &cx, int n, int logC) {
 #pragma unroll 2
     for (int it = 0; it < iters; it++) {
       const int j = q + (it << logC);
-      const int4 r = *(const int4 *)&cx.lds->rows[j][0];
-      const int2 hx = *(const int2 *)&cx.lds->rows[j][4];
+      const int4 r = *(const int4 *)&rows[j][0];
+      const int2 hx = *(const int2 *)&rows[j][4];
       const UVal u = u_exact(rc, r.x, r.y, r.z, hx.x, hx.y);
       neg |= (int32_t)((uint64_t)u.hi >> 32);
     }
@@ -224,37 +250,169 @@ __device__ __forceinline__ void test_batch(CX &cx, int n, int logC) {
   const uint64_t gm = C >= 64 ? ~0ull : ((1ull << C) - 1);
   const bool surv = valid && q == 0 && ((rej >> (p << logC)) & gm) == 0;
   uint64_t sm = ballot(surv);
+  if constexpr (CX::stats) cx.wide += (uint32_t)__builtin_popcountll(sm);
   while (sm) { // rare: no point strictly below this candidate (a cell or a tie)
     const int l = __builtin_ctzll(sm);
     sm &= sm - 1;
     int32_t b[8];
 #pragma unroll
     for (int i = 0; i < 8; i++) b[i] = rl32(rc[i], l);
-    decide_exact(cx, b);
+    decide_exact(cx, b, rec_table(b));
   }
+  const uint32_t nold = (uint32_t)__builtin_popcountll(ballot(valid && q == 0 && t == cx.old.t));
+  cx.old.recs -= nold;
+  cx.neu.recs -= (uint32_t)n - nold;
   cx.head = (cx.head + n) & (DENSE_RING - 1);
   cx.nrec -= n;
 }
 
-// The triples of a node with three spatial columns left (k - 2 points
-// chosen, lowest `low`), within the work unit's constraints.
-template <int K, class CX>
-__device__ __forceinline__ void triple_stage(CX &cx, const St<3> &st, int low) {
+// 2^logC lanes per candidate for a last batch of n < 64 records
+__device__ __forceinline__ int chunk_log(int n) {
+  int logC = 0;
+  while (logC < 6 && (n << (logC + 1)) <= 64) logC++;
+  return logC;
+}
+
+// One setup pass: up to 64 pending triples, the older node's first, then the
+// newer's.  Each lane derives its triple's cofactors from its node's rows;
+// the triples with D != 0 are appended to the record ring.
+template <class CX>
+__device__ __forceinline__ void setup_pass(CX &cx) {
   constexpr bool S = CX::stats;
   const int lane = lane_id();
-  // 1. the node's rows (s0, s1, s2, h as lo/hi words); whether every |h_j| < 2^31
+  NodeInfo &A = cx.old, &B = cx.neu;
+  const uint32_t nA = min(64u, A.r_hi - A.r_cur);
+  const uint32_t nB = min(64u - nA, B.r_hi - B.r_cur);
+  const bool inA = (uint32_t)lane < nA;
+  const bool act = inA || (uint32_t)lane < nA + nB;
+  const int t = inA ? A.t : B.t;
+  const uint32_t r = inA ? A.r_cur + (uint32_t)lane : B.r_cur + ((uint32_t)lane - nA);
+  Div dv;
+  dv.e = inA ? A.e : B.e;
+  dv.inv = inA ? A.inv : B.inv;
+  const bool prevneg = inA ? A.prevneg : B.prevneg;
+  A.r_cur += nA;
+  B.r_cur += nB;
+  int c1, c2, c3;
+  unrank3(act ? r : 0, &c1, &c2, &c3); // (an inactive lane reads rows 2, 1, 0, in range)
+  const int32_t *R1 = cx.lds->rows[t][c1], *R2 = cx.lds->rows[t][c2], *R3 = cx.lds->rows[t][c3];
+  const int4 a1 = *(const int4 *)R1, a2 = *(const int4 *)R2, a3 = *(const int4 *)R3;
+  const int2 x1 = *(const int2 *)(R1 + 4), x2 = *(const int2 *)(R2 + 4), x3 = *(const int2 *)(R3 + 4);
+  // heights split at bit 29: h = hh 2^29 + l, 0 <= l < 2^29
+  const int32_t hh1 = x1.x, l1 = x1.y, hh2 = x2.x, l2 = x2.y, hh3 = x3.x, l3 = x3.y;
+  const int32_t s01 = a1.x, s11 = a1.y, s21 = a1.z;
+  const int32_t s02 = a2.x, s12 = a2.y, s22 = a2.z;
+  const int32_t s03 = a3.x, s13 = a3.y, s23 = a3.z;
+  // 2 x 2 minors of rows c1, c2 (T+2 minors), spatial and with the height column
+  const int32_t m01 = exdiv32((int64_t)s01 * s12 - (int64_t)s11 * s02, dv);
+  const int32_t m02 = exdiv32((int64_t)s01 * s22 - (int64_t)s21 * s02, dv);
+  const int32_t m12 = exdiv32((int64_t)s11 * s22 - (int64_t)s21 * s12, dv);
+  const int64_t m0h = exdiv_limbs((int64_t)s01 * hh2 - (int64_t)hh1 * s02, (int64_t)s01 * l2 - (int64_t)l1 * s02, dv);
+  const int64_t m1h = exdiv_limbs((int64_t)s11 * hh2 - (int64_t)hh1 * s12, (int64_t)s11 * l2 - (int64_t)l1 * s12, dv);
+  const int64_t m2h = exdiv_limbs((int64_t)s21 * hh2 - (int64_t)hh1 * s22, (int64_t)s21 * l2 - (int64_t)l1 * s22, dv);
+  // 3 x 3 minors of rows c1, c2, c3 (T+3 minors) by expansion along row c3:
+  // the spatial one D first, then, with row c3 multiplied by the
+  // orientation sign(D) sign(prev) (every minor below is linear in it), the
+  // coefficients of u_j: k0 = -H0, k1 = H1, k2 = -H2 (H_a: column a deleted)
+  const int32_t D = exdiv32((int64_t)s03 * m12 - (int64_t)s13 * m02 + (int64_t)s23 * m01, dv);
+  const bool nz = act && D != 0;
+  if constexpr (S) {
+    cx.setups++;
+    cx.triples += nA + nB;
+  }
+  const bool flip = (D < 0) != prevneg;
+  const int32_t P0 = flip ? -s03 : s03, P1 = flip ? -s13 : s13, P2 = flip ? -s23 : s23;
+  const int32_t Ph = flip ? -hh3 : hh3, Pl = flip ? -l3 : l3;
+  int64_t Hi, Lo;
+  Hi = (int64_t)(-Ph) * m12, Lo = (int64_t)(-Pl) * m12;
+  acc_limbs(Hi, Lo, -P1, m2h);
+  acc_limbs(Hi, Lo, P2, m1h);
+  const int64_t k0 = exdiv_limbs(Hi, Lo, dv); // -H0, columns s1, s2, h
+  Hi = (int64_t)Ph * m02, Lo = (int64_t)Pl * m02;
+  acc_limbs(Hi, Lo, P0, m2h);
+  acc_limbs(Hi, Lo, -P2, m0h);
+  const int64_t k1 = exdiv_limbs(Hi, Lo, dv); // H1, columns s0, s2, h
+  Hi = (int64_t)(-Ph) * m01, Lo = (int64_t)(-Pl) * m01;
+  acc_limbs(Hi, Lo, -P0, m1h);
+  acc_limbs(Hi, Lo, P1, m0h);
+  const int64_t k2 = exdiv_limbs(Hi, Lo, dv); // -H2, columns s0, s1, h
+  const int32_t d = flip ? -D : D;
+  const uint64_t m = ballot(nz);
+  if (nz) {
+    const uint32_t below = (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1));
+    const int slot = (cx.head + cx.nrec + (int)below) & (DENSE_RING - 1);
+    const bool fits = k0 == (int64_t)(int32_t)k0 && k1 == (int64_t)(int32_t)k1 && k2 == (int64_t)(int32_t)k2;
+    int4 x, y;
+    x.x = (int32_t)(k0 & DENSE_LMASK), x.y = (int32_t)(k0 >> DENSE_LIMB);
+    x.z = (int32_t)(k1 & DENSE_LMASK), x.w = (int32_t)(k1 >> DENSE_LIMB);
+    y.x = (int32_t)(k2 & DENSE_LMASK), y.y = (int32_t)(k2 >> DENSE_LIMB);
+    y.z = d, y.w = c1 | (c2 << 8) | (c3 << 16) | (fits ? REC_FITS : 0) | (t << REC_TABLE_BIT);
+    *(int4 *)&cx.lds->rec[slot][0] = x;
+    *(int4 *)&cx.lds->rec[slot][4] = y;
+  }
+  const int addA = __builtin_popcountll(m & ((nA >= 64 ? ~0ull : (1ull << nA) - 1)));
+  const int added = __builtin_popcountll(m);
+  if constexpr (S) cx.leaves += (uint32_t)added;
+  A.recs += (uint32_t)addA;
+  B.recs += (uint32_t)(added - addA);
+  cx.nrec += added;
+  wave_sync_lds();
+}
+
+// Setup passes while at least `need` triples are pending (need = 1: all),
+// each followed by a full test batch when 64 records wait.
+template <class CX>
+__device__ __forceinline__ bool run_setups(CX &cx, uint32_t need) {
+  for (;;) {
+    const uint32_t pend = (cx.old.r_hi - cx.old.r_cur) + (cx.neu.r_hi - cx.neu.r_cur);
+    if (pend == 0 || pend < need) return true;
+    if (!charge(cx, 1)) return false;
+    setup_pass(cx);
+    if (cx.nrec >= 64) {
+      if (!charge(cx, 1)) return false;
+      test_batch(cx, 64, 0);
+    }
+  }
+}
+
+// A node with three spatial columns left (k - 2 points chosen, lowest
+// `low`): its rows go into the table of the older node, after that node's
+// triples and records are finished; its triples (within the work unit's
+// constraints) join the pending ones, and full setup passes run.
+template <int K, class CX>
+__device__ __forceinline__ void triple_stage(CX &cx, const St<3> &st, int low) {
+  const int lane = lane_id();
+  const int t = cx.old.t; // the older node's table is reused
+  // 1. finish the older node
+  {
+    NodeInfo &O = cx.old;
+    while (O.r_cur < O.r_hi) {
+      if (!charge(cx, 1)) return;
+      setup_pass(cx);
+      if (cx.nrec >= 64) {
+        if (!charge(cx, 1)) return;
+        test_batch(cx, 64, 0);
+      }
+    }
+    if (O.recs > 0) { // at most 63 records wait: they are the oldest, test all
+      if (!charge(cx, 1)) return;
+      test_batch(cx, cx.nrec, chunk_log(cx.nrec));
+    }
+  }
+  // 2. the node's rows (s0, s1, s2, h's low word, h split at bit 29)
+  bool fit;
   {
     const int64_t h = ((int64_t)st.H1 << 31) + (int64_t)st.H0;
     int4 r;
     r.x = st.s[0], r.y = st.s[1], r.z = st.s[2], r.w = (int32_t)(uint32_t)h;
-    *(int4 *)&cx.lds->rows[lane][0] = r;
+    *(int4 *)&cx.lds->rows[t][lane][0] = r;
     int2 hx;
     hx.x = (int32_t)(h >> DENSE_LIMB), hx.y = (int32_t)(h & DENSE_LMASK);
-    *(int2 *)&cx.lds->rows[lane][4] = hx;
-    cx.rows_fit = ballot(h != (int64_t)(int32_t)h) == 0;
+    *(int2 *)&cx.lds->rows[t][lane][4] = hx;
+    fit = ballot(h != (int64_t)(int32_t)h) == 0;
   }
   wave_sync_lds();
-  // 2. colex ranks of the triples allowed below this node
+  // 3. colex ranks of the triples allowed below this node
   constexpr int P = K - 2; // position of c1 among the candidate's elements
   uint32_t r_lo = 0, r_hi = 0;
   {
@@ -285,89 +443,34 @@ __device__ __forceinline__ void triple_stage(CX &cx, const St<3> &st, int low) {
       }
     }
   }
-  if constexpr (S) cx.nodes++;
-  if (r_hi <= r_lo) return;
-  const Div dv = make_div(st.prev);
-  const bool prevneg = st.prev < 0;
-  // 3. setup passes of 64 triples: cofactors, compaction of D != 0
-  for (uint32_t base = r_lo; base < r_hi; base += 64) {
-    if (!charge(cx, 1)) return;
-    const uint32_t r = base + (uint32_t)lane;
-    const bool act = r < r_hi;
-    int c1, c2, c3;
-    unrank3(act ? r : r_lo, &c1, &c2, &c3);
-    const int32_t *R1 = cx.lds->rows[c1], *R2 = cx.lds->rows[c2], *R3 = cx.lds->rows[c3];
-    const int4 a1 = *(const int4 *)R1, a2 = *(const int4 *)R2, a3 = *(const int4 *)R3;
-    const int2 x1 = *(const int2 *)(R1 + 4), x2 = *(const int2 *)(R2 + 4), x3 = *(const int2 *)(R3 + 4);
-    // heights split at bit 29: h = hh 2^29 + l, 0 <= l < 2^29
-    const int32_t hh1 = x1.x, l1 = x1.y, hh2 = x2.x, l2 = x2.y, hh3 = x3.x, l3 = x3.y;
-    const int32_t s01 = a1.x, s11 = a1.y, s21 = a1.z;
-    const int32_t s02 = a2.x, s12 = a2.y, s22 = a2.z;
-    const int32_t s03 = a3.x, s13 = a3.y, s23 = a3.z;
-    // 2 x 2 minors of rows c1, c2 (T+2 minors), spatial and with the height column
-    const int32_t m01 = exdiv32((int64_t)s01 * s12 - (int64_t)s11 * s02, dv);
-    const int32_t m02 = exdiv32((int64_t)s01 * s22 - (int64_t)s21 * s02, dv);
-    const int32_t m12 = exdiv32((int64_t)s11 * s22 - (int64_t)s21 * s12, dv);
-    const int64_t m0h = exdiv_limbs((int64_t)s01 * hh2 - (int64_t)hh1 * s02, (int64_t)s01 * l2 - (int64_t)l1 * s02, dv);
-    const int64_t m1h = exdiv_limbs((int64_t)s11 * hh2 - (int64_t)hh1 * s12, (int64_t)s11 * l2 - (int64_t)l1 * s12, dv);
-    const int64_t m2h = exdiv_limbs((int64_t)s21 * hh2 - (int64_t)hh1 * s22, (int64_t)s21 * l2 - (int64_t)l1 * s22, dv);
-    // 3 x 3 minors of rows c1, c2, c3 (T+3 minors) by expansion along row c3:
-    // the spatial one D first, then, with row c3 multiplied by the
-    // orientation sign(D) sign(prev) (every minor below is linear in it), the
-    // coefficients of u_j: k0 = -H0, k1 = H1, k2 = -H2 (H_a: column a deleted)
-    const int32_t D = exdiv32((int64_t)s03 * m12 - (int64_t)s13 * m02 + (int64_t)s23 * m01, dv);
-    const bool nz = act && D != 0;
-    if constexpr (S) {
-      cx.setups++;
-      cx.triples += (uint32_t)__builtin_popcountll(ballot(act));
-    }
-    const bool flip = (D < 0) != prevneg;
-    const int32_t P0 = flip ? -s03 : s03, P1 = flip ? -s13 : s13, P2 = flip ? -s23 : s23;
-    const int32_t Ph = flip ? -hh3 : hh3, Pl = flip ? -l3 : l3;
-    int64_t Hi, Lo;
-    Hi = (int64_t)(-Ph) * m12, Lo = (int64_t)(-Pl) * m12;
-    acc_limbs(Hi, Lo, -P1, m2h);
-    acc_limbs(Hi, Lo, P2, m1h);
-    const int64_t k0 = exdiv_limbs(Hi, Lo, dv); // -H0, columns s1, s2, h
-    Hi = (int64_t)Ph * m02, Lo = (int64_t)Pl * m02;
-    acc_limbs(Hi, Lo, P0, m2h);
-    acc_limbs(Hi, Lo, -P2, m0h);
-    const int64_t k1 = exdiv_limbs(Hi, Lo, dv); // H1, columns s0, s2, h
-    Hi = (int64_t)(-Ph) * m01, Lo = (int64_t)(-Pl) * m01;
-    acc_limbs(Hi, Lo, -P0, m1h);
-    acc_limbs(Hi, Lo, P1, m0h);
-    const int64_t k2 = exdiv_limbs(Hi, Lo, dv); // -H2, columns s0, s1, h
-    const int32_t d = flip ? -D : D;
-    const uint64_t m = ballot(nz);
-    if (nz) {
-      const uint32_t below = (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1));
-      const int slot = (cx.head + cx.nrec + (int)below) & (DENSE_RING - 1);
-      const bool fits = k0 == (int64_t)(int32_t)k0 && k1 == (int64_t)(int32_t)k1 && k2 == (int64_t)(int32_t)k2;
-      int4 x, y;
-      x.x = (int32_t)(k0 & DENSE_LMASK), x.y = (int32_t)(k0 >> DENSE_LIMB);
-      x.z = (int32_t)(k1 & DENSE_LMASK), x.w = (int32_t)(k1 >> DENSE_LIMB);
-      y.x = (int32_t)(k2 & DENSE_LMASK), y.y = (int32_t)(k2 >> DENSE_LIMB);
-      y.z = d, y.w = c1 | (c2 << 8) | (c3 << 16) | (fits ? REC_FITS : 0);
-      *(int4 *)&cx.lds->rec[slot][0] = x;
-      *(int4 *)&cx.lds->rec[slot][4] = y;
-    }
-    const int added = __builtin_popcountll(m);
-    if constexpr (S) cx.leaves += (uint32_t)added;
-    cx.nrec += added;
-    wave_sync_lds();
-    if (cx.nrec >= 64) {
-      if (!charge(cx, 1)) return;
-      test_batch(cx, 64, 0);
-    }
+  if constexpr (CX::stats) cx.nodes++;
+  cx.old = cx.neu;
+  {
+    NodeInfo &Nn = cx.neu;
+    const Div dv = make_div(st.prev);
+    Nn.t = t;
+    Nn.chosen = cx.chosen;
+    Nn.inv = dv.inv;
+    Nn.e = dv.e;
+    Nn.r_cur = r_lo;
+    Nn.r_hi = r_hi > r_lo ? r_hi : r_lo;
+    Nn.recs = 0;
+    Nn.prevneg = st.prev < 0;
+    Nn.rows_fit = fit;
   }
-  // 4. the node's last records, each candidate's points over 64 / 2^logC lanes
-  if (cx.nrec > 0) {
+  // 4. full setup passes over the pending triples of both nodes
+  (void)run_setups(cx, 64);
+}
+
+// End of a work unit: every pending triple and record.
+template <class CX>
+__device__ __forceinline__ void dense_flush(CX &cx) {
+  if (!run_setups(cx, 1)) return;
+  while (cx.nrec > 0) {
     if (!charge(cx, 1)) return;
-    int logC = 0;
-    while (logC < 6 && (cx.nrec << (logC + 1)) <= 64) logC++;
-    test_batch(cx, cx.nrec, logC);
+    const int n = cx.nrec < 64 ? cx.nrec : 64;
+    test_batch(cx, n, n < 64 ? chunk_log(n) : 0);
   }
-  wave_sync_lds(); // the next node rewrites the rows
 }
 
 // Range of the next element at depth T (as next_range in enum_device.hpp).
@@ -470,32 +573,70 @@ __device__ __forceinline__ void dense_tile(CX &cx, const SysDesc &sd, const int3
   DLevel<K, 0, CX>::run(cx, st, base);
 }
 
-template <int KLO, int KHI, int MODE>
-__device__ __forceinline__ void dense_unit(const Tile &tl, const SysDesc &sd, const int32_t *__restrict__ pts,
-                                           const int64_t *__restrict__ hts, SysAcc *__restrict__ acc,
-                                           DevCounters *__restrict__ cnt, const CellSink &sink, DenseLds *lds) {
-  using CX = DCtx<MODE>;
+// Add the wave's tally (the unit's lower facets, plus those of earlier
+// units' candidates decided during it) and work counts to the system's
+// accumulators, and clear them; a unit that ran out of steps reports an error.
+template <class CX>
+__device__ __forceinline__ void dense_commit(CX &cx, const SysDesc &sd, SysAcc *a, DevCounters *cnt, bool unit) {
   constexpr bool S = CX::stats;
   const int lane = lane_id();
-  CX cx;
-  cx.N = sd.N;
-  cx.k = sd.k;
-  cx.j = lane;
+  wave_sync_lds();
+  const bool abandoned = cx.left <= 0;
+  if (lane == 0 && abandoned) atomicOr(&cnt->error, 1u);
+  if (lane == 0 && !abandoned) {
+    const unsigned long long sum = cx.lds->tally.acc;
+    const uint32_t cells = cx.lds->tally.cells, tie = cx.lds->tally.tie;
+    if (sum | cells | tie) {
+      const unsigned long long old = atomicAdd((unsigned long long *)&a->lo, sum);
+      if (old + sum < old) atomicAdd((unsigned long long *)&a->hi, 1ull);
+      atomicAdd((unsigned long long *)&a->cells, (unsigned long long)cells);
+      if (tie) atomicOr(&a->tie, 1u);
+    }
+    if constexpr (S) {
+      const unsigned long long n = (unsigned long long)sd.N, t = (unsigned long long)(sd.N - sd.k - 1);
+      atomicAdd((unsigned long long *)&cnt->inner, (unsigned long long)cx.inner);
+      atomicAdd((unsigned long long *)&cnt->sp_upd, (unsigned long long)cx.sp_upd);
+      atomicAdd((unsigned long long *)&cnt->pruned, (unsigned long long)cx.pruned);
+      // (no ridges in this schedule: its nodes with three spatial columns
+      // left, setup passes, test batches and the candidates decided exactly
+      // after the batch test take the ridge, ridge-step, leaf-step and
+      // empty-step counters)
+      atomicAdd((unsigned long long *)&cnt->leaves, (unsigned long long)cx.leaves);
+      atomicAdd((unsigned long long *)&cnt->rsteps, (unsigned long long)cx.setups);
+      atomicAdd((unsigned long long *)&cnt->lsteps, (unsigned long long)cx.tests);
+      atomicAdd((unsigned long long *)&cnt->triples, (unsigned long long)cx.triples);
+      atomicAdd((unsigned long long *)&cnt->lempty, (unsigned long long)cx.wide);
+      atomicAdd((unsigned long long *)&cnt->ridges, (unsigned long long)cx.nodes);
+      if (unit) {
+        atomicAdd((unsigned long long *)&cnt->dunits, 1ull);
+        atomicAdd((unsigned long long *)&cnt->tiles, 1ull);
+      }
+      atomicAdd((unsigned long long *)&cnt->w_inner, n * cx.inner);
+      atomicAdd((unsigned long long *)&cnt->w_spatial, n * cx.sp_upd);
+      atomicAdd((unsigned long long *)&cnt->w_leaves, t * cx.leaves);
+    }
+    cx.lds->tally.acc = 0;
+    cx.lds->tally.cells = 0;
+    cx.lds->tally.tie = 0;
+  }
+  cx.inner = cx.sp_upd = cx.pruned = cx.nodes = cx.triples = cx.leaves = cx.setups = cx.tests = cx.wide = 0;
+  wave_sync_lds();
+}
+
+// The depth-first walk of one work unit.  The setup and test pipeline is
+// not drained at its end: the next unit of the same system goes on with the
+// pending triples and records (their rows stay in the tables), so that the
+// passes and batches stay full across unit boundaries.
+template <int KLO, int KHI, class CX>
+__device__ __forceinline__ void dense_unit(CX &cx, const Tile &tl, const SysDesc &sd, const int32_t *__restrict__ pts,
+                                           const int64_t *__restrict__ hts) {
   cx.mask = tl.mask;
   cx.L = __builtin_popcountll(tl.mask);
   cx.c_lo = tl.c_lo;
   cx.c_hi = tl.c_hi;
-  cx.lds = lds;
-  cx.head = 0;
-  cx.nrec = 0;
-  cx.inner = cx.sp_upd = cx.pruned = cx.nodes = cx.triples = cx.leaves = cx.setups = cx.tests = 0;
-  cx.sink = sink;
-  if (lane == 0) {
-    lds->tally.acc = 0;
-    lds->tally.cells = 0;
-    lds->tally.tie = 0;
-  }
   {
+    // (k + 3) steps per candidate, plus room for the passes and batches of
+    // up to 64 + 64 candidates carried over from the previous unit
     const uint64_t cand = unit_candidates(sd.k, tl.mask, tl.c_lo, tl.c_hi);
     const uint64_t b = cand * (uint64_t)(sd.k + 3) + 256;
     cx.left = b > 0x7FFFFFF0ull ? 0x7FFFFFF0 : (int32_t)b;
@@ -512,37 +653,6 @@ __device__ __forceinline__ void dense_unit(const Tile &tl, const SysDesc &sd, co
 #undef BDEG_DCASE
     default:
       break;
-  }
-  wave_sync_lds();
-  const bool abandoned = cx.left <= 0;
-  if (lane == 0 && abandoned) atomicOr(&cnt->error, 1u);
-  if (lane == 0 && !abandoned) {
-    const unsigned long long sum = lds->tally.acc;
-    const uint32_t cells = lds->tally.cells, tie = lds->tally.tie;
-    if (sum | cells | tie) {
-      SysAcc *a = &acc[tl.sys];
-      const unsigned long long old = atomicAdd((unsigned long long *)&a->lo, sum);
-      if (old + sum < old) atomicAdd((unsigned long long *)&a->hi, 1ull);
-      atomicAdd((unsigned long long *)&a->cells, (unsigned long long)cells);
-      if (tie) atomicOr(&a->tie, 1u);
-    }
-    if constexpr (S) {
-      const unsigned long long n = (unsigned long long)sd.N, t = (unsigned long long)(sd.N - sd.k - 1);
-      atomicAdd((unsigned long long *)&cnt->inner, (unsigned long long)cx.inner);
-      atomicAdd((unsigned long long *)&cnt->sp_upd, (unsigned long long)cx.sp_upd);
-      atomicAdd((unsigned long long *)&cnt->pruned, (unsigned long long)cx.pruned);
-      // (no ridges in this schedule: setup passes and test batches take the
-      // ridge- and leaf-step counters)
-      atomicAdd((unsigned long long *)&cnt->leaves, (unsigned long long)cx.leaves);
-      atomicAdd((unsigned long long *)&cnt->rsteps, (unsigned long long)cx.setups);
-      atomicAdd((unsigned long long *)&cnt->lsteps, (unsigned long long)cx.tests);
-      atomicAdd((unsigned long long *)&cnt->triples, (unsigned long long)cx.triples);
-      atomicAdd((unsigned long long *)&cnt->dunits, 1ull);
-      atomicAdd((unsigned long long *)&cnt->tiles, 1ull);
-      atomicAdd((unsigned long long *)&cnt->w_inner, n * cx.inner);
-      atomicAdd((unsigned long long *)&cnt->w_spatial, n * cx.sp_upd);
-      atomicAdd((unsigned long long *)&cnt->w_leaves, t * cx.leaves);
-    }
   }
 }
 
@@ -561,6 +671,31 @@ dense_kernel(const SysDesc *__restrict__ sys, const int32_t *__restrict__ pts, c
   __shared__ DenseLds lds_all[4]; // one per wavefront of the block (at most 256 threads)
   DenseLds *lds = &lds_all[threadIdx.x >> 6];
   if (rerun && rerun[0] == 0) return;
+  using CX = DCtx<MODE>;
+  CX cx;
+  cx.j = lane;
+  cx.lds = lds;
+  cx.sink = sink;
+  cx.head = 0;
+  cx.nrec = 0;
+  cx.old.t = 0;
+  cx.neu.t = 1;
+  cx.old.r_cur = cx.old.r_hi = cx.neu.r_cur = cx.neu.r_hi = 0;
+  cx.old.recs = cx.neu.recs = 0;
+  cx.old.chosen = cx.neu.chosen = 0;
+  cx.old.inv = cx.neu.inv = 1;
+  cx.old.e = cx.neu.e = 0;
+  cx.old.prevneg = cx.neu.prevneg = false;
+  cx.old.rows_fit = cx.neu.rows_fit = true;
+  cx.inner = cx.sp_upd = cx.pruned = cx.nodes = cx.triples = cx.leaves = cx.setups = cx.tests = cx.wide = 0;
+  cx.left = 1;
+  if (lane == 0) {
+    lds->tally.acc = 0;
+    lds->tally.cells = 0;
+    lds->tally.tie = 0;
+  }
+  uint32_t cur_sys = 0xFFFFFFFFu;
+  SysDesc sd{};
   for (;;) {
     // every lane joins the claim; lane 0's result is read by index (no
     // lane-dependent branch around the loop's exit test)
@@ -569,8 +704,24 @@ dense_kernel(const SysDesc *__restrict__ sys, const int32_t *__restrict__ pts, c
     if (t >= n_tiles) break;
     const Tile tl = tiles[t];
     if (rerun && rerun[1 + tl.sys] == 0) continue;
-    const SysDesc sd = sys[tl.sys];
-    dense_unit<KLO, KHI, MODE>(tl, sd, pts, hts, acc, cnt, sink, lds);
+    if (tl.sys != cur_sys) {
+      if (cur_sys != 0xFFFFFFFFu) { // another system: finish the previous one's candidates
+        cx.left = 256;
+        dense_flush(cx);
+        dense_commit(cx, sd, &acc[cur_sys], cnt, false);
+      }
+      cur_sys = tl.sys;
+      sd = sys[tl.sys];
+      cx.N = sd.N;
+      cx.k = sd.k;
+    }
+    dense_unit<KLO, KHI>(cx, tl, sd, pts, hts);
+    dense_commit(cx, sd, &acc[cur_sys], cnt, true);
+  }
+  if (cur_sys != 0xFFFFFFFFu) {
+    cx.left = 256;
+    dense_flush(cx);
+    dense_commit(cx, sd, &acc[cur_sys], cnt, false);
   }
 }
 

@@ -95,10 +95,12 @@ void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t ma
     d.lift_bits = h.lift_bits;
     d.npad_log2 = npad_log2_for(h.N);
     uint64_t cost = max_cost;
+    bool dense = dense_ok(h.pts.data(), h.N, h.k, (1ull << h.lift_bits) - 1);
     if (sched) {
       const BucketSchedule &b = sched->e[h.k][d.npad_log2];
       if (b.npad_log2 >= d.npad_log2 && b.npad_log2 <= 6) d.npad_log2 = b.npad_log2;
       if (b.unit_cost > 0) cost = b.unit_cost;
+      if (b.dense == 0) dense = false;
     }
     // every system draws from the single-system stream (index 0), so its
     // liftings, and hence attempts and cells, do not depend on its position
@@ -106,7 +108,7 @@ void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t ma
     d.lift_key = lift_key(h.seed, 0u, h.attempt);
     d.seed = h.seed;
     d.sys_index = 0;
-    d.flags = dense_ok(h.pts.data(), h.N, h.k, (1ull << h.lift_bits) - 1) ? SYS_DENSE : 0;
+    d.flags = dense ? SYS_DENSE : 0;
     job.sys.push_back(d);
     job.pts.insert(job.pts.end(), h.pts.begin(), h.pts.end());
     ht += h.N;

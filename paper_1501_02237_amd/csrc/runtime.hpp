@@ -65,11 +65,13 @@ struct Job {
 };
 
 // Work schedule of a batch, per bucket of systems with the same k and the same
-// smallest lane-group width (npad_log2_for(N)): the lane-group width the
-// systems run with (npad_log2 >= the smallest; 6 = one group per wavefront,
-// the single-group kernel variant) and the work-unit size cap.  Chosen by the
+// smallest lane-group width (npad_log2_for(N)): the kernel (lane-dense, for
+// systems it is certified for, or lanes as points), the lane-group width the
+// lanes-as-points kernel runs with (npad_log2 >= the smallest; 6 = one group
+// per wavefront, the single-group kernel variant) and the work-unit size cap.  Chosen by the
 // autotuner (tune.cpp) and persisted as a JSON table.
 struct BucketSchedule {
+  int dense = -1;         // kernel: 1 lane-dense, 0 lanes as points, -1 unset (lane-dense when certified)
   int npad_log2 = 0;      // 0: unset (the default: the smallest width)
   uint64_t unit_cost = 0; // 0: unset (the default: choose_max_cost of the whole job)
   float ms = 0;           // measured device time of the bucket's tuning set with this schedule

@@ -2,9 +2,10 @@
 //
 // The table is a small JSON document:
 //   {"device": "gfx950", "entries": [
-//     {"k": 5, "npad_min": 4, "npad": 4, "unit_cost": 1024, "ms": 0.41, "systems": 412},
+//     {"k": 5, "npad_min": 4, "dense": 1, "npad": 4, "unit_cost": 1024, "ms": 0.41, "systems": 412},
 //     ...]}
-// one entry per bucket (k, smallest lane-group width as log2).  The reader
+// one entry per bucket (k, smallest lane-group width as log2); "dense" is the
+// kernel (1 lane-dense, 0 lanes as points; absent: lane-dense when certified).  The reader
 // accepts exactly what the writer produces (flat objects of numbers and
 // strings inside "entries"); anything else is an error and leaves the table
 // empty, so a damaged file never changes a schedule silently.
@@ -24,7 +25,7 @@ namespace {
 
 // numbers of one flat JSON object {"key": value, ...}; false on a syntax error
 bool parse_object(const char *&p, const char *end, ScheduleTable &t) {
-  long long k = -1, npad_min = -1, npad = 0, systems = 0;
+  long long k = -1, npad_min = -1, npad = 0, systems = 0, dense = -1;
   unsigned long long cost = 0;
   double ms = 0;
   ++p; // '{'
@@ -60,10 +61,13 @@ bool parse_object(const char *&p, const char *end, ScheduleTable &t) {
     else if (key == "unit_cost") cost = (unsigned long long)v;
     else if (key == "ms") ms = v;
     else if (key == "systems") systems = (long long)v;
+    else if (key == "dense") dense = (long long)v;
   }
-  if (k < 1 || k > BDEG_MAX_K || npad_min < 3 || npad_min > 6 || npad < npad_min || npad > 6 || cost > (1ull << 26))
+  if (k < 1 || k > BDEG_MAX_K || npad_min < 3 || npad_min > 6 || npad < npad_min || npad > 6 || cost > (1ull << 26) ||
+      dense < -1 || dense > 1)
     return false;
   BucketSchedule &b = t.e[k][npad_min];
+  b.dense = (int)dense;
   b.npad_log2 = (int)npad;
   b.unit_cost = cost;
   b.ms = (float)ms;
@@ -122,8 +126,10 @@ int schedule_write(const char *path, const ScheduleTable &t) {
     for (int g = 3; g <= 6; g++) {
       const BucketSchedule &b = t.e[k][g];
       if (b.npad_log2 == 0 && b.unit_cost == 0) continue;
-      fprintf(f, "%s\n  {\"k\": %d, \"npad_min\": %d, \"npad\": %d, \"unit_cost\": %llu, \"ms\": %.4f, \"systems\": %d}",
-              first ? "" : ",", k, g, b.npad_log2, (unsigned long long)b.unit_cost, (double)b.ms, b.systems);
+      fprintf(f,
+              "%s\n  {\"k\": %d, \"npad_min\": %d, \"dense\": %d, \"npad\": %d, \"unit_cost\": %llu, \"ms\": %.4f, "
+              "\"systems\": %d}",
+              first ? "" : ",", k, g, b.dense, b.npad_log2, (unsigned long long)b.unit_cost, (double)b.ms, b.systems);
       first = false;
     }
   fprintf(f, "\n]}\n");

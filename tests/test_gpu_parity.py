@@ -482,6 +482,7 @@ def test_batch_tuner_writes_a_table_and_keeps_results(tmp_path):
     assert {e["k"] for e in table["entries"]} == ks
     for e in table["entries"]:
         assert e["npad_min"] <= e["npad"] <= 6 and e["ms"] > 0 and e["systems"] > 0
+        assert e["dense"] in (-1, 0, 1)
 
 
 # ------------------------------------------------------------------ serving
