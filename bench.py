@@ -39,25 +39,32 @@ PEAK_ALU = 256 * 4 * 32 * 2.4e9
 
 # HBM traffic of one headline enumeration launch (n = 36 system), from the
 # rocprofv3 FETCH_SIZE and WRITE_SIZE passes summarised in
-# profiles/enum_kernel_large36_pmc.md (KiB per dispatch, mean of the timed
+# profiles/enum_kernel_large36.md (KiB per dispatch, mean of the timed
 # dispatches), each scaled by what the counter reads for a device copy of
-# known size in the same run.  Valid only for the kernel source and the
-# work-unit sizing the counters were taken on: any change to the listed files
-# makes `traffic` null.
+# known size in the same run.  Valid only for the kernel sources and the
+# work-unit sizing (the tuned schedule table) the counters were taken on: any
+# change to the listed files makes `traffic` null.
 TRAFFIC = {
     "sources": ("enum_device.hpp", "enum_dense.hpp", "exact_div.hpp", "kernels_k10.hip", "runtime.cpp",
                 "bdeg_internal.hpp", "lifting.hpp"),
-    "sha256": "",
-    "fetch_kib": 0.0, "fetch_scale": 1.0,
-    "write_kib": 0.0, "write_scale": 1.0,
+    "table": os.path.join("tuning", "gfx950.json"),
+    "sha256": "0353d0a17f1b03116abbd0d70099ccc6d8340f87f73f4f6d14c5f01da614cce9",
+    "fetch_kib": 27088.3, "fetch_scale": 262144.0 / 131088.6,
+    "write_kib": 18323.0, "write_scale": 262144.0 / 262144.0,
 }
 
 
 def traffic_bytes():
     h = hashlib.sha256()
+    pkg = os.path.join(ROOT, "paper_1501_02237_amd")
     for f in TRAFFIC["sources"]:
-        with open(os.path.join(ROOT, "paper_1501_02237_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(pkg, "csrc", f), "rb") as fh:
             h.update(fh.read())
+    try:
+        with open(os.path.join(pkg, TRAFFIC["table"]), "rb") as fh:
+            h.update(fh.read())
+    except OSError:
+        return None
     if h.hexdigest() != TRAFFIC["sha256"]:
         return None
     return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])

@@ -107,10 +107,9 @@ typedef struct {
   /* lane-dense schedule (BDEG_SCHED_AUTO): it creates no ridges; there
      `ridges` counts its nodes with three spatial columns left, `leaves` the
      candidates with D != 0 it tested, ridge_steps its setup passes,
-     leaf_steps its test batches and empty_steps the candidates no point
-     rejected in the batch test, decided exactly one by one (the cells, the
-     ties and the rare candidates whose points below all lie in the test's
-     rounding band) */
+     leaf_steps its test batches and empty_steps the candidates with no
+     point strictly below them, decided one by one with lanes as points (the
+     cells and the ties) */
   uint64_t triples;           /* candidates set up at nodes with three spatial columns left (any D) */
   uint64_t dense_units;       /* work units run by the lane-dense kernel */
   float kernel_ms;            /* device time of the enumeration kernel, HIP events */
