@@ -26,25 +26,31 @@
 //     takes 64 records and loops over the points, every lane testing its own
 //     candidate against point j (row j is one broadcast LDS read), so all 64
 //     lanes do the same useful work and consecutive points are independent
-//     chains.
-//   * The two most recent nodes keep their rows in two LDS tables, so a setup
-//     pass or a test batch may hold candidates of both: passes and batches
-//     stay full although a node has only a few dozen candidates.  The
-//     pipeline also runs on across the work units of one system; only a
-//     change of system, or the end, drains it (a last batch of fewer than 64
-//     records splits each candidate's points over several lanes).
-//   * The rare candidates that no point rejects are decided exactly with
-//     lanes as points: the zero count tells a lower facet (exactly the k + 1
-//     vertices vanish) from a tie.
+//     chains.  The test is four 32 x 32 -> 64 multiply-adds per point: exact
+//     when the record's coefficients and the node's heights fit 31 and 32
+//     bits; otherwise both are shifted right by one amount and the sum,
+//     with a bound on what the shift dropped, proves a point below or leaves
+//     the candidate to the exact decision.
+//   * The three most recent nodes keep their rows in three LDS tables, so a
+//     setup pass or a test batch may hold candidates of all of them: passes
+//     and batches stay full although most nodes have only a few candidates
+//     (a node whose lowest chosen point is c has C(c, 3)).  A node is
+//     finished only when a new node needs its table; that drains the
+//     pipeline (a last batch of fewer than 64 records splits each
+//     candidate's points over several lanes), and the next two new nodes
+//     then find their tables free.  The pipeline also runs on across the
+//     work units of one system; a change of system, or the end, drains it.
+//   * The rare candidates with no point proved below are decided exactly
+//     with lanes as points: a point strictly below rejects, and the zero
+//     count tells a lower facet (exactly the k + 1 vertices vanish) from a
+//     tie.
 //
 // Widths (certified on the host for these systems: spatial minors < 2^30,
-// height minors < 2^59): when a node's heights and a record's coefficients
-// fit int32, u_j is four 32 x 32 -> 64 products (each below 2^61) summed in
-// int64; otherwise heights and height minors are split as x = xh 2^29 + xl
-// with 0 <= xl < 2^29, so every product is still a 32 x 32 -> 64
-// multiply-add, the low limbs sum below 2^61 and the high limbs below 2^62,
-// and u_j < 0 exactly when its high part (with the low part's carry) is
-// negative.
+// height minors < 2^59): the cofactors are formed with heights and height
+// minors split as x = xh 2^29 + xl, 0 <= xl < 2^29, so every product is a
+// 32 x 32 -> 64 multiply-add; the exact decision sums u_j the same way (low
+// limbs below 2^61, high limbs below 2^62; u_j < 0 exactly when its high
+// part, with the low part's carry, is negative).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -58,25 +64,37 @@ namespace dev {
 constexpr int DENSE_LIMB = 29;
 constexpr int64_t DENSE_LMASK = (1ll << DENSE_LIMB) - 1;
 constexpr int DENSE_RING = 128; // candidate records per wavefront (a power of two >= 2 * 64)
+constexpr int DENSE_TABLES = 3; // row tables: the most recent nodes in flight
 
-// Per-wavefront LDS: the point rows of the two most recent nodes and the
-// record ring.
+// What the setup passes and the exact decisions need of the node in a row
+// table (kept in LDS, not in scalar registers).
+struct TableInfo {
+  uint64_t inv;    // the 2-adic inverse of the node's pivot (sign folded in)
+  uint64_t chosen; // its chosen points (vertices shared by its candidates)
+  uint32_t e;      // the pivot's 2-adic valuation
+  uint32_t prevneg; // pivot < 0
+  uint32_t sig;    // the table holds h >> sig, which fits int32
+  uint32_t band;   // the largest |s0| + |s1| + |s2| of its points (BAND_UNSET: not needed yet)
+};
+constexpr uint32_t BAND_UNSET = 0xFFFFFFFFu;
+
+// Per-wavefront LDS: the point rows of the most recent nodes and the record
+// ring.
 struct alignas(16) DenseLds {
-  alignas(16) int32_t rows[2][64][8];     // s0, s1, s2, h (its low word), hh, hl; two unused words keep rows 32-byte aligned
-  alignas(16) int32_t rec[DENSE_RING][8]; // kl0, kh0, kl1, kh1, kl2, kh2, d, vertices | REC_FITS | table
+  int4 rowS[DENSE_TABLES][64];            // s0, s1, s2, h >> sig
+  int2 rowH[DENSE_TABLES][64];            // h split at bit 29: hh, hl
+  alignas(16) int32_t rec[DENSE_RING][8]; // kl0, kh0, kl1, kh1, kl2, kh2, d, vertices | table | shift
+  TableInfo info[DENSE_TABLES];
   Tally tally;
 };
+// four blocks of four waves fit a compute unit's 160 KiB
+static_assert(16 * sizeof(DenseLds) <= 160 * 1024, "lane-dense LDS limits occupancy below four waves per SIMD");
 
 // One node held in a row table (wave-uniform values).
 struct NodeInfo {
-  int t;               // its row table (0 or 1)
-  uint64_t chosen;     // its chosen points (vertices shared by its candidates)
-  uint64_t inv;        // the 2-adic inverse of its pivot (sign folded in)
-  uint32_t e;          // the pivot's 2-adic valuation
+  int t;               // its row table (and TableInfo)
   uint32_t r_cur, r_hi; // its triples still to set up: colex ranks [r_cur, r_hi)
   uint32_t recs;       // its records in the ring
-  bool prevneg;        // pivot < 0
-  bool rows_fit;       // every height of the node fits int32
 };
 
 template <int MODE>
@@ -89,10 +107,11 @@ struct DCtx {
   int c_lo, c_hi;  // sibling run at the first free level
   uint64_t chosen; // chosen points of the current depth-first node
   DenseLds *lds;
-  // The two most recent nodes, older and newer (each in its own row
-  // table).  A setup pass takes the older node's triples first, then the
-  // newer's; the record ring is in the same order.
-  NodeInfo old, neu;
+  // The most recent nodes, oldest first (each in its own row table).  A
+  // setup pass takes the oldest node's triples first, then the next ones';
+  // the record ring is in the same order.  (Indexed by constants only, so
+  // that they stay in scalar registers.)
+  NodeInfo nd[DENSE_TABLES];
   int head, nrec;  // record ring: first record and count (wave-uniform)
   int32_t left;    // watchdog budget (as in enum_device.hpp)
   uint32_t inner, sp_upd, pruned, nodes, triples, leaves, setups, tests, wide;
@@ -147,11 +166,33 @@ __device__ __forceinline__ void acc_limbs(int64_t &Hi, int64_t &Lo, int32_t a, i
 
 // A candidate record: its coefficients split at bit 29 (k = kh 2^29 + kl,
 // 0 <= kl < 2^29) as kl0, kh0, kl1, kh1, kl2, kh2, then d, then
-// c1 | c2 << 8 | c3 << 16, REC_FITS when every |k_a| < 2^31, and its node
-// table at REC_TABLE_BIT.
-constexpr int REC_FITS = 1 << 24;
+// c1 | c2 << 8 | c3 << 16, its node table in the two bits at REC_TABLE_BIT
+// and the shift of its filter test (below) in the five bits at REC_SHIFT_BIT.
 constexpr int REC_TABLE_BIT = 25;
-__device__ __forceinline__ int rec_table(const int32_t *rc) { return (rc[7] >> REC_TABLE_BIT) & 1; }
+constexpr int REC_SHIFT_BIT = 27;
+__device__ __forceinline__ int rec_table(const int32_t *rc) { return (rc[7] >> REC_TABLE_BIT) & 3; }
+__device__ __forceinline__ int rec_shift(const int32_t *rc) { return (int)((uint32_t)rc[7] >> REC_SHIFT_BIT); }
+
+// floor((kh 2^29 + kl) / 2^sg), 0 <= kl < 2^29, for a quotient that fits
+// int32 (sg <= 31): for sg < 29 the wrapping sum has the quotient's bits.
+__device__ __forceinline__ int32_t limb_shift(int32_t kl, int32_t kh, int sg) {
+  return sg >= DENSE_LIMB ? (kh >> (sg - DENSE_LIMB))
+                          : (int32_t)(((uint32_t)kh << (DENSE_LIMB - sg)) + ((uint32_t)kl >> sg));
+}
+
+// Wave-wide maximum of an unsigned value (every lane active): a row-wise DPP
+// shift scan, then the row broadcasts; lane 63 ends with the maximum.
+__device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false)); // row_shr:1
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false)); // row_shr:2
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false)); // row_shr:4
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false)); // row_shr:8
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false)); // row_bcast:15
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false)); // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+
 
 // u_j = k0 s0 + k1 s1 + k2 s2 + d h exactly, as (hi, lo) with
 // u = 2^29 hi + (lo mod 2^29): every product is a 32 x 32 -> 64 multiply-add
@@ -175,15 +216,16 @@ __device__ __forceinline__ UVal u_exact(const int32_t *rc, int32_t s0, int32_t s
 template <class CX>
 __device__ __forceinline__ void decide_exact(CX &cx, const int32_t *rc, int t) {
   const int lane = lane_id();
-  const int32_t *row = cx.lds->rows[t][lane];
-  const UVal u = u_exact(rc, row[0], row[1], row[2], row[4], row[5]);
+  const int4 row = cx.lds->rowS[t][lane];
+  const int2 hx = cx.lds->rowH[t][lane];
+  const UVal u = u_exact(rc, row.x, row.y, row.z, hx.x, hx.y);
   const bool on = u.hi == 0 && (u.lo & DENSE_LMASK) == 0;
   const uint64_t zero = ballot(on && lane < cx.N);
   const uint64_t below = ballot(u.hi < 0 && lane < cx.N);
-  if (below) return; // (the batch test is exact: cannot happen)
+  if (below) return; // a point below within the filter's band
   const int vtx = rc[7];
   const int c1 = vtx & 255, c2 = (vtx >> 8) & 255, c3 = (vtx >> 16) & 255;
-  const uint64_t verts = (t == cx.old.t ? cx.old.chosen : cx.neu.chosen) | (1ull << c1) | (1ull << c2) | (1ull << c3);
+  const uint64_t verts = cx.lds->info[t].chosen | (1ull << c1) | (1ull << c2) | (1ull << c3);
   if (zero != verts) {
     if (lane == 0) cx.lds->tally.tie = 1;
     return;
@@ -210,38 +252,42 @@ __device__ __forceinline__ void test_batch(CX &cx, int n, int logC) {
     const int4 b = *(const int4 *)&cx.lds->rec[slot][4];
     rc[0] = a.x, rc[1] = a.y, rc[2] = a.z, rc[3] = a.w, rc[4] = b.x, rc[5] = b.y, rc[6] = b.z, rc[7] = b.w;
   }
-  // Exact test.  When the node's heights and every record's coefficients
-  // fit int32 (the common case for 20-bit liftings), u_j is four products of
-  // 32-bit values, each below 2^61 in magnitude, summed exactly in int64;
-  // otherwise the split-limb form.  A candidate with some u_j < 0 is
-  // rejected; one that no point rejects is decided exactly below.
+  // Filter test, exact in its rejections.  A record's shift sg makes its
+  // coefficients k_a >> sg fit 31 bits and its node's heights h >> sg fit 32
+  // (the row table holds h >> sn, sn <= sg; a lane shifts on by sg - sn).
+  // Then u_j = 2^sg v_j + e_j, v_j = sum_a (k_a >> sg) s_aj + d (h_j >> sg),
+  // with 0 <= the dropped low parts < 2^sg, so |e_j| < 2^sg (|s0| + |s1| +
+  // |s2| + |d|) and v_j + B + |d| <= 0 (B: the node's largest |s0| + |s1| +
+  // |s2|) proves u_j < 0.  With sg = 0 (coefficients and heights fit, the
+  // common case for 20-bit liftings) v_j is u_j and the test is exact.
+  // Every sum is four products below 2^61 plus the band: below 2^63.  A
+  // candidate with a point proved below is rejected; one without is decided
+  // exactly below.
   const int iters = (cx.N + (1 << logC) - 1) >> logC; // rows past N are zero rows
   const int t = rec_table(rc);
-  const bool tfit = t == cx.old.t ? cx.old.rows_fit : cx.neu.rows_fit;
-  const bool narrow = ballot(valid && !((rc[7] & REC_FITS) && tfit)) == 0;
-  const int32_t(*rows)[8] = cx.lds->rows[t];
+  const int sg = rec_shift(rc);
+  const uint2 sb = *(const uint2 *)&cx.lds->info[t].sig; // (sig, band) of the record's table
+  const int dl = sg - (int)sb.x;
+  const int32_t x0 = limb_shift(rc[0], rc[1], sg), x1 = limb_shift(rc[2], rc[3], sg), x2 = limb_shift(rc[4], rc[5], sg);
+  const int32_t d = rc[6];
+  const int64_t bnd = sg > 0 ? (int64_t)sb.y + (d < 0 ? -(int64_t)d : (int64_t)d) - 1 : 0;
+  const int4 *rowS = cx.lds->rowS[t];
   int32_t neg = 0;
-  if (narrow) {
-    // each |k_a| < 2^31: the 32-bit values themselves (wrapping arithmetic
-    // rebuilds them exactly from the limbs)
-    const int32_t k0 = (int32_t)(((uint32_t)rc[1] << DENSE_LIMB) + (uint32_t)rc[0]);
-    const int32_t k1 = (int32_t)(((uint32_t)rc[3] << DENSE_LIMB) + (uint32_t)rc[2]);
-    const int32_t k2 = (int32_t)(((uint32_t)rc[5] << DENSE_LIMB) + (uint32_t)rc[4]);
+  if (ballot(valid && dl != 0) == 0) {
 #pragma unroll 4
     for (int it = 0; it < iters; it++) {
       const int j = q + (it << logC); // < 64: 2^logC divides 64 and N <= 64
-      const int4 r = *(const int4 *)&rows[j][0];
-      const int64_t u = (int64_t)r.x * k0 + (int64_t)r.y * k1 + (int64_t)r.z * k2 + (int64_t)r.w * rc[6];
-      neg |= (int32_t)((uint64_t)u >> 32);
+      const int4 r = rowS[j];
+      const int64_t v = bnd + (int64_t)r.x * x0 + (int64_t)r.y * x1 + (int64_t)r.z * x2 + (int64_t)r.w * d;
+      neg |= (int32_t)((uint64_t)v >> 32);
     }
   } else {
-#pragma unroll 2
+#pragma unroll 4
     for (int it = 0; it < iters; it++) {
       const int j = q + (it << logC);
-      const int4 r = *(const int4 *)&rows[j][0];
-      const int2 hx = *(const int2 *)&rows[j][4];
-      const UVal u = u_exact(rc, r.x, r.y, r.z, hx.x, hx.y);
-      neg |= (int32_t)((uint64_t)u.hi >> 32);
+      const int4 r = rowS[j];
+      const int64_t v = bnd + (int64_t)r.x * x0 + (int64_t)r.y * x1 + (int64_t)r.z * x2 + (int64_t)(r.w >> dl) * d;
+      neg |= (int32_t)((uint64_t)v >> 32);
     }
   }
   if constexpr (CX::stats) cx.tests++;
@@ -251,7 +297,7 @@ __device__ __forceinline__ void test_batch(CX &cx, int n, int logC) {
   const bool surv = valid && q == 0 && ((rej >> (p << logC)) & gm) == 0;
   uint64_t sm = ballot(surv);
   if constexpr (CX::stats) cx.wide += (uint32_t)__builtin_popcountll(sm);
-  while (sm) { // rare: no point strictly below this candidate (a cell or a tie)
+  while (sm) { // rare: no point proved below (a cell, a tie, or a point within the band)
     const int l = __builtin_ctzll(sm);
     sm &= sm - 1;
     int32_t b[8];
@@ -259,9 +305,9 @@ __device__ __forceinline__ void test_batch(CX &cx, int n, int logC) {
     for (int i = 0; i < 8; i++) b[i] = rl32(rc[i], l);
     decide_exact(cx, b, rec_table(b));
   }
-  const uint32_t nold = (uint32_t)__builtin_popcountll(ballot(valid && q == 0 && t == cx.old.t));
-  cx.old.recs -= nold;
-  cx.neu.recs -= (uint32_t)n - nold;
+#pragma unroll
+  for (int i = 0; i < DENSE_TABLES; i++)
+    cx.nd[i].recs -= (uint32_t)__builtin_popcountll(ballot(valid && q == 0 && t == cx.nd[i].t));
   cx.head = (cx.head + n) & (DENSE_RING - 1);
   cx.nrec -= n;
 }
@@ -273,31 +319,47 @@ __device__ __forceinline__ int chunk_log(int n) {
   return logC;
 }
 
-// One setup pass: up to 64 pending triples, the older node's first, then the
-// newer's.  Each lane derives its triple's cofactors from its node's rows;
-// the triples with D != 0 are appended to the record ring.
+// Lane mask of the bits [lo, hi) (lo <= hi <= 64).
+__device__ __forceinline__ uint64_t bit_range(uint32_t lo, uint32_t hi) {
+  const uint64_t below_hi = hi >= 64 ? ~0ull : (1ull << hi) - 1;
+  const uint64_t below_lo = lo >= 64 ? ~0ull : (1ull << lo) - 1;
+  return below_hi & ~below_lo;
+}
+
+// One setup pass: up to 64 pending triples, the oldest node's first, then
+// the next ones'.  Each lane derives its triple's cofactors from its node's
+// rows; the triples with D != 0 are appended to the record ring.
 template <class CX>
 __device__ __forceinline__ void setup_pass(CX &cx) {
   constexpr bool S = CX::stats;
   const int lane = lane_id();
-  NodeInfo &A = cx.old, &B = cx.neu;
-  const uint32_t nA = min(64u, A.r_hi - A.r_cur);
-  const uint32_t nB = min(64u - nA, B.r_hi - B.r_cur);
-  const bool inA = (uint32_t)lane < nA;
-  const bool act = inA || (uint32_t)lane < nA + nB;
-  const int t = inA ? A.t : B.t;
-  const uint32_t r = inA ? A.r_cur + (uint32_t)lane : B.r_cur + ((uint32_t)lane - nA);
+  uint32_t cnt[DENSE_TABLES];
+  uint32_t base = 0, r = 0;
+  int t = cx.nd[0].t;
+#pragma unroll
+  for (int i = 0; i < DENSE_TABLES; i++) {
+    NodeInfo &A = cx.nd[i];
+    const uint32_t n = min(64u - base, A.r_hi - A.r_cur);
+    if ((uint32_t)lane >= base && (uint32_t)lane < base + n) {
+      t = A.t;
+      r = A.r_cur + ((uint32_t)lane - base);
+    }
+    A.r_cur += n;
+    cnt[i] = n;
+    base += n;
+  }
+  const bool act = (uint32_t)lane < base;
+  const TableInfo ti = cx.lds->info[t];
   Div dv;
-  dv.e = inA ? A.e : B.e;
-  dv.inv = inA ? A.inv : B.inv;
-  const bool prevneg = inA ? A.prevneg : B.prevneg;
-  A.r_cur += nA;
-  B.r_cur += nB;
+  dv.e = ti.e;
+  dv.inv = ti.inv;
+  const bool prevneg = ti.prevneg != 0;
   int c1, c2, c3;
   unrank3(act ? r : 0, &c1, &c2, &c3); // (an inactive lane reads rows 2, 1, 0, in range)
-  const int32_t *R1 = cx.lds->rows[t][c1], *R2 = cx.lds->rows[t][c2], *R3 = cx.lds->rows[t][c3];
-  const int4 a1 = *(const int4 *)R1, a2 = *(const int4 *)R2, a3 = *(const int4 *)R3;
-  const int2 x1 = *(const int2 *)(R1 + 4), x2 = *(const int2 *)(R2 + 4), x3 = *(const int2 *)(R3 + 4);
+  const int4 *RS = cx.lds->rowS[t];
+  const int2 *RH = cx.lds->rowH[t];
+  const int4 a1 = RS[c1], a2 = RS[c2], a3 = RS[c3];
+  const int2 x1 = RH[c1], x2 = RH[c2], x3 = RH[c3];
   // heights split at bit 29: h = hh 2^29 + l, 0 <= l < 2^29
   const int32_t hh1 = x1.x, l1 = x1.y, hh2 = x2.x, l2 = x2.y, hh3 = x3.x, l3 = x3.y;
   const int32_t s01 = a1.x, s11 = a1.y, s21 = a1.z;
@@ -318,7 +380,7 @@ __device__ __forceinline__ void setup_pass(CX &cx) {
   const bool nz = act && D != 0;
   if constexpr (S) {
     cx.setups++;
-    cx.triples += nA + nB;
+    cx.triples += base;
   }
   const bool flip = (D < 0) != prevneg;
   const int32_t P0 = flip ? -s03 : s03, P1 = flip ? -s13 : s13, P2 = flip ? -s23 : s23;
@@ -338,23 +400,42 @@ __device__ __forceinline__ void setup_pass(CX &cx) {
   const int64_t k2 = exdiv_limbs(Hi, Lo, dv); // -H2, columns s0, s1, h
   const int32_t d = flip ? -D : D;
   const uint64_t m = ballot(nz);
+  // the filter's shift: k_a >> sg within [-2^30, 2^30), and at least the table's
+  const uint64_t mk = (uint64_t)(k0 ^ (k0 >> 63)) | (uint64_t)(k1 ^ (k1 >> 63)) | (uint64_t)(k2 ^ (k2 >> 63));
+  const int sg = max(max(64 - __builtin_clzll(mk | 1) - 30, 0), (int)ti.sig);
+  if (ballot(nz && sg > 0 && ti.band == BAND_UNSET)) {
+    // a shifted record in a table whose band was not needed so far
+    // (the band is taken eagerly for tables whose heights are shifted)
+#pragma unroll
+    for (int i = 0; i < DENSE_TABLES; i++)
+      if (ballot(nz && sg > 0 && ti.band == BAND_UNSET && t == i)) {
+        const int4 rw = cx.lds->rowS[i][lane];
+        const uint32_t b = wave_umax((uint32_t)abs(rw.x) + (uint32_t)abs(rw.y) + (uint32_t)abs(rw.z));
+        if (lane == 0) cx.lds->info[i].band = b;
+      }
+    wave_sync_lds();
+  }
   if (nz) {
     const uint32_t below = (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1));
     const int slot = (cx.head + cx.nrec + (int)below) & (DENSE_RING - 1);
-    const bool fits = k0 == (int64_t)(int32_t)k0 && k1 == (int64_t)(int32_t)k1 && k2 == (int64_t)(int32_t)k2;
     int4 x, y;
     x.x = (int32_t)(k0 & DENSE_LMASK), x.y = (int32_t)(k0 >> DENSE_LIMB);
     x.z = (int32_t)(k1 & DENSE_LMASK), x.w = (int32_t)(k1 >> DENSE_LIMB);
     y.x = (int32_t)(k2 & DENSE_LMASK), y.y = (int32_t)(k2 >> DENSE_LIMB);
-    y.z = d, y.w = c1 | (c2 << 8) | (c3 << 16) | (fits ? REC_FITS : 0) | (t << REC_TABLE_BIT);
+    y.z = d, y.w = c1 | (c2 << 8) | (c3 << 16) | (t << REC_TABLE_BIT) | (sg << REC_SHIFT_BIT);
     *(int4 *)&cx.lds->rec[slot][0] = x;
     *(int4 *)&cx.lds->rec[slot][4] = y;
   }
-  const int addA = __builtin_popcountll(m & ((nA >= 64 ? ~0ull : (1ull << nA) - 1)));
   const int added = __builtin_popcountll(m);
   if constexpr (S) cx.leaves += (uint32_t)added;
-  A.recs += (uint32_t)addA;
-  B.recs += (uint32_t)(added - addA);
+  {
+    uint32_t lo = 0;
+#pragma unroll
+    for (int i = 0; i < DENSE_TABLES; i++) {
+      cx.nd[i].recs += (uint32_t)__builtin_popcountll(m & bit_range(lo, lo + cnt[i]));
+      lo += cnt[i];
+    }
+  }
   cx.nrec += added;
   wave_sync_lds();
 }
@@ -364,7 +445,9 @@ __device__ __forceinline__ void setup_pass(CX &cx) {
 template <class CX>
 __device__ __forceinline__ bool run_setups(CX &cx, uint32_t need) {
   for (;;) {
-    const uint32_t pend = (cx.old.r_hi - cx.old.r_cur) + (cx.neu.r_hi - cx.neu.r_cur);
+    uint32_t pend = 0;
+#pragma unroll
+    for (int i = 0; i < DENSE_TABLES; i++) pend += cx.nd[i].r_hi - cx.nd[i].r_cur;
     if (pend == 0 || pend < need) return true;
     if (!charge(cx, 1)) return false;
     setup_pass(cx);
@@ -376,16 +459,16 @@ __device__ __forceinline__ bool run_setups(CX &cx, uint32_t need) {
 }
 
 // A node with three spatial columns left (k - 2 points chosen, lowest
-// `low`): its rows go into the table of the older node, after that node's
+// `low`): its rows go into the table of the oldest node, after that node's
 // triples and records are finished; its triples (within the work unit's
 // constraints) join the pending ones, and full setup passes run.
 template <int K, class CX>
 __device__ __forceinline__ void triple_stage(CX &cx, const St<3> &st, int low) {
   const int lane = lane_id();
-  const int t = cx.old.t; // the older node's table is reused
-  // 1. finish the older node
+  const int t = cx.nd[0].t; // the oldest node's table is reused
+  // 1. finish the oldest node
   {
-    NodeInfo &O = cx.old;
+    NodeInfo &O = cx.nd[0];
     while (O.r_cur < O.r_hi) {
       if (!charge(cx, 1)) return;
       setup_pass(cx);
@@ -394,22 +477,39 @@ __device__ __forceinline__ void triple_stage(CX &cx, const St<3> &st, int low) {
         test_batch(cx, 64, 0);
       }
     }
-    if (O.recs > 0) { // at most 63 records wait: they are the oldest, test all
+    if (O.recs > 0) { // at most 63 records wait, its own the oldest: test all
       if (!charge(cx, 1)) return;
       test_batch(cx, cx.nrec, chunk_log(cx.nrec));
     }
   }
   // 2. the node's rows (s0, s1, s2, h's low word, h split at bit 29)
-  bool fit;
+  // (its heights' shift sig: the smallest with h >> sig in [-2^31, 2^31);
+  // its band, the largest |s0| + |s1| + |s2|, now when sig > 0, else when a
+  // record first needs it; padding lanes hold zeros)
+  uint32_t sig = 0, band = BAND_UNSET;
   {
     const int64_t h = ((int64_t)st.H1 << 31) + (int64_t)st.H0;
+    if (ballot(h != (int64_t)(int32_t)h) != 0) {
+      sig = wave_umax((uint32_t)(64 - __builtin_clzll((uint64_t)(h ^ (h >> 63)) | 1))) - 31;
+      band = wave_umax((uint32_t)abs(st.s[0]) + (uint32_t)abs(st.s[1]) + (uint32_t)abs(st.s[2]));
+    }
     int4 r;
-    r.x = st.s[0], r.y = st.s[1], r.z = st.s[2], r.w = (int32_t)(uint32_t)h;
-    *(int4 *)&cx.lds->rows[t][lane][0] = r;
+    r.x = st.s[0], r.y = st.s[1], r.z = st.s[2], r.w = (int32_t)(h >> sig);
+    cx.lds->rowS[t][lane] = r;
     int2 hx;
     hx.x = (int32_t)(h >> DENSE_LIMB), hx.y = (int32_t)(h & DENSE_LMASK);
-    *(int2 *)&cx.lds->rows[t][lane][4] = hx;
-    fit = ballot(h != (int64_t)(int32_t)h) == 0;
+    cx.lds->rowH[t][lane] = hx;
+  }
+  if (lane == 0) {
+    const Div dv = make_div(st.prev);
+    TableInfo ti;
+    ti.inv = dv.inv;
+    ti.chosen = cx.chosen;
+    ti.e = dv.e;
+    ti.prevneg = st.prev < 0;
+    ti.sig = sig;
+    ti.band = band;
+    cx.lds->info[t] = ti;
   }
   wave_sync_lds();
   // 3. colex ranks of the triples allowed below this node
@@ -444,21 +544,16 @@ __device__ __forceinline__ void triple_stage(CX &cx, const St<3> &st, int low) {
     }
   }
   if constexpr (CX::stats) cx.nodes++;
-  cx.old = cx.neu;
+#pragma unroll
+  for (int i = 0; i + 1 < DENSE_TABLES; i++) cx.nd[i] = cx.nd[i + 1];
   {
-    NodeInfo &Nn = cx.neu;
-    const Div dv = make_div(st.prev);
+    NodeInfo &Nn = cx.nd[DENSE_TABLES - 1];
     Nn.t = t;
-    Nn.chosen = cx.chosen;
-    Nn.inv = dv.inv;
-    Nn.e = dv.e;
     Nn.r_cur = r_lo;
     Nn.r_hi = r_hi > r_lo ? r_hi : r_lo;
     Nn.recs = 0;
-    Nn.prevneg = st.prev < 0;
-    Nn.rows_fit = fit;
   }
-  // 4. full setup passes over the pending triples of both nodes
+  // 4. full setup passes over the pending triples of the nodes in flight
   (void)run_setups(cx, 64);
 }
 
@@ -658,9 +753,9 @@ __device__ __forceinline__ void dense_unit(CX &cx, const Tile &tl, const SysDesc
 
 // Waves per SIMD the dense kernel is compiled for: the depth-first states
 // above the triple stage grow with k (about (k^2 + 7k) / 2 registers), the
-// triple stage adds a fixed working set; six waves is also the LDS limit
-// (24 KiB per block of four).
-constexpr int dense_waves(int k) { return k <= 6 ? 6 : k <= 10 ? 4 : k <= 13 ? 3 : 2; }
+// triple stage adds a fixed working set; four waves is also the LDS limit
+// (34.4 KiB per block of four waves, four blocks per compute unit).
+constexpr int dense_waves(int k) { return k <= 10 ? 4 : k <= 13 ? 3 : 2; }
 
 template <int KLO, int KHI, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dense_waves(KHI))))
@@ -678,15 +773,12 @@ dense_kernel(const SysDesc *__restrict__ sys, const int32_t *__restrict__ pts, c
   cx.sink = sink;
   cx.head = 0;
   cx.nrec = 0;
-  cx.old.t = 0;
-  cx.neu.t = 1;
-  cx.old.r_cur = cx.old.r_hi = cx.neu.r_cur = cx.neu.r_hi = 0;
-  cx.old.recs = cx.neu.recs = 0;
-  cx.old.chosen = cx.neu.chosen = 0;
-  cx.old.inv = cx.neu.inv = 1;
-  cx.old.e = cx.neu.e = 0;
-  cx.old.prevneg = cx.neu.prevneg = false;
-  cx.old.rows_fit = cx.neu.rows_fit = true;
+#pragma unroll
+  for (int i = 0; i < DENSE_TABLES; i++) {
+    cx.nd[i].t = i;
+    cx.nd[i].r_cur = cx.nd[i].r_hi = 0;
+    cx.nd[i].recs = 0;
+  }
   cx.inner = cx.sp_upd = cx.pruned = cx.nodes = cx.triples = cx.leaves = cx.setups = cx.tests = cx.wide = 0;
   cx.left = 1;
   if (lane == 0) {
