@@ -374,7 +374,7 @@ def main():
         h = plain_leg(bd, torch, gen.cfg2_system(), a.steps, a.warmup)
         st = h.pop("stats")
         h["work"] = {key: st[key] for key in ("tiles", "inner_nodes", "ridges", "leaves", "triples", "ridge_steps",
-                                              "leaf_steps", "empty_steps", "dense_units", "pruned")}
+                                              "leaf_steps", "empty_steps", "dense_units", "quads", "pruned")}
         print(json.dumps(h), flush=True)
         return
 
@@ -387,7 +387,7 @@ def main():
     if a.only == "headline":
         st = h.pop("stats")
         h["work"] = {key: st[key] for key in ("tiles", "inner_nodes", "ridges", "leaves", "triples", "ridge_steps",
-                                              "leaf_steps", "empty_steps", "dense_units", "pruned")}
+                                              "leaf_steps", "empty_steps", "dense_units", "quads", "pruned")}
         print(json.dumps(h), flush=True)
         return
     st = h["stats"]

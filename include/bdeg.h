@@ -108,10 +108,14 @@ typedef struct {
      `ridges` counts its nodes with three spatial columns left, `leaves` the
      candidates with D != 0 it tested, ridge_steps its setup passes,
      leaf_steps its test batches and empty_steps the candidates with no
-     point strictly below them, decided one by one with lanes as points (the
-     cells and the ties) */
-  uint64_t triples;           /* candidates set up at nodes with three spatial columns left (any D) */
+     point proved below them by the batch test, decided one by one with
+     lanes as points (the cells, the ties, and candidates whose points below
+     all lie within the test's band) */
+  uint64_t triples;           /* candidates it set up (any D): triples of nodes with three
+                                 spatial columns left and tail quadruples */
   uint64_t dense_units;       /* work units run by the lane-dense kernel */
+  uint64_t quads;             /* the tail quadruples among `triples` (set up from nodes with
+                                 four spatial columns left) */
   float kernel_ms;            /* device time of the enumeration kernel, HIP events */
   float total_ms;             /* device time of the whole device pass (clear, lift, enumerate) */
   int32_t captured;           /* 1: the device pass replays captured HIP graphs; 0: plain launches */
@@ -248,7 +252,7 @@ int bdeg_nvol_points(const int32_t *points, const int64_t *heights, int32_t N, i
  *   overlapped a call on the same array would race with it.
  */
 #define BDEG_NOALLOC_MAX_UNITS (1 << 17)
-#define BDEG_NOALLOC_SCRATCH_BYTES ((size_t)BDEG_NOALLOC_MAX_UNITS * 16u + 16384u)
+#define BDEG_NOALLOC_SCRATCH_BYTES ((size_t)BDEG_NOALLOC_MAX_UNITS * 16u + 32768u)
 int bdeg_nvol_points_noalloc(const int32_t *points, const int64_t *heights, int32_t N, int32_t k,
                              uint64_t rank_lo, uint64_t rank_hi, bdeg_u128 *nvol, int32_t *tie,
                              uint64_t *cells);

@@ -35,7 +35,7 @@ PRUNE_MAX_PREFIXES = 1 << 24
 NOALLOC_MAX_UNITS = 1 << 17
 SCHED_AUTO = 0
 SCHED_POINTS = 1
-NOALLOC_SCRATCH_BYTES = NOALLOC_MAX_UNITS * 16 + 16384
+NOALLOC_SCRATCH_BYTES = NOALLOC_MAX_UNITS * 16 + 32768
 U64_MAX = (1 << 64) - 1
 
 
@@ -71,7 +71,7 @@ class Stats(ctypes.Structure):
         ("pruned", ctypes.c_uint64), ("leaves", ctypes.c_uint64), ("tiles", ctypes.c_uint64),
         ("ridge_steps", ctypes.c_uint64), ("leaf_steps", ctypes.c_uint64), ("empty_steps", ctypes.c_uint64),
         ("point_inner", ctypes.c_uint64), ("point_spatial", ctypes.c_uint64), ("point_ridges", ctypes.c_uint64),
-        ("leaf_points", ctypes.c_uint64), ("triples", ctypes.c_uint64), ("dense_units", ctypes.c_uint64),
+        ("leaf_points", ctypes.c_uint64), ("triples", ctypes.c_uint64), ("dense_units", ctypes.c_uint64), ("quads", ctypes.c_uint64),
         ("kernel_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
         ("captured", ctypes.c_int32), ("redraws", ctypes.c_int32),
     ]

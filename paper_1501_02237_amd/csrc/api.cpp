@@ -600,6 +600,7 @@ int bdeg_batch_profile(bdeg_batch *b) {
   b->stats.leaf_points = cnt.w_leaves;
   b->stats.triples = cnt.triples;
   b->stats.dense_units = cnt.dunits;
+  b->stats.quads = cnt.quads;
   return BDEG_OK;
 }
 

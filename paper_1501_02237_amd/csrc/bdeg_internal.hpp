@@ -61,9 +61,9 @@ struct DevCounters {
   // the same work weighted by the points it touches (exact over systems of
   // different N): N * inner, N * sp_upd, N * ridges, (N - k - 1) * leaves
   uint64_t w_inner, w_spatial, w_ridges, w_leaves;
-  // lane-dense kernel: candidates set up at nodes with three spatial columns
-  // left (with or without D = 0), and the units it ran
-  uint64_t triples, dunits;
+  // lane-dense kernel: candidates set up (with or without D = 0), the units
+  // it ran, and the candidates among the first set up as tail quadruples
+  uint64_t triples, dunits, quads;
   uint32_t next_tile; // dynamic work queue head
   uint32_t error;     // a work unit exceeded its step budget (watchdog)
 };

@@ -65,6 +65,7 @@ constexpr int DENSE_LIMB = 29;
 constexpr int64_t DENSE_LMASK = (1ll << DENSE_LIMB) - 1;
 constexpr int DENSE_RING = 128; // candidate records per wavefront (a power of two >= 2 * 64)
 constexpr int DENSE_TABLES = 3; // row tables: the most recent nodes in flight
+constexpr int DENSE_TAIL = 7;   // children below this point: quadruples set up from their parent
 
 // What the setup passes and the exact decisions need of the node in a row
 // table (kept in LDS, not in scalar registers).
@@ -85,6 +86,10 @@ struct alignas(16) DenseLds {
   int2 rowH[DENSE_TABLES][64];            // h split at bit 29: hh, hl
   alignas(16) int32_t rec[DENSE_RING][8]; // kl0, kh0, kl1, kh1, kl2, kh2, d, vertices | table | shift
   TableInfo info[DENSE_TABLES];
+  // rows of the node whose tail quadruples are set up (four spatial columns)
+  int4 qS[64];  // s0, s1, s2, s3
+  int32_t qh[64]; // h >> its shift
+  int2 qx[8];   // h split at bit 29 (hh, hl) of the points below DENSE_TAIL
   Tally tally;
 };
 // four blocks of four waves fit a compute unit's 160 KiB
@@ -114,7 +119,7 @@ struct DCtx {
   NodeInfo nd[DENSE_TABLES];
   int head, nrec;  // record ring: first record and count (wave-uniform)
   int32_t left;    // watchdog budget (as in enum_device.hpp)
-  uint32_t inner, sp_upd, pruned, nodes, triples, leaves, setups, tests, wide;
+  uint32_t inner, sp_upd, pruned, nodes, triples, leaves, setups, tests, wide, quads;
   CellSink sink;
 };
 
@@ -458,6 +463,46 @@ __device__ __forceinline__ bool run_setups(CX &cx, uint32_t need) {
   }
 }
 
+// Colex ranks [r_lo, r_hi) of the triples {c1 > c2 > c3} below `low` that
+// complete the current node within the work unit's constraints (rank =
+// C(c1,3) + C(c2,2) + c3; the unit fixes its top elements and restricts
+// the element after them to [c_lo, c_hi]).
+template <int K, class CX>
+__device__ __forceinline__ void triple_range(const CX &cx, int low, uint32_t *rlo, uint32_t *rhi) {
+  constexpr int P = K - 2; // position of c1 among the candidate's elements
+  uint32_t r_lo = 0, r_hi = 0;
+  {
+    uint64_t below = cx.mask & ((1ull << low) - 1);
+    if (cx.L < P) {
+      r_hi = c3_of(low);
+    } else if (cx.L == P) {
+      const int lo = max(cx.c_lo, 2), hi = min(cx.c_hi, low - 1);
+      if (hi >= lo) r_lo = c3_of(lo), r_hi = c3_of(hi + 1);
+    } else {
+      const int f1 = 63 - __builtin_clzll(below);
+      below &= ~(1ull << f1);
+      const uint32_t base1 = c3_of(f1);
+      if (cx.L == P + 1) {
+        const int lo = max(cx.c_lo, 1), hi = min(cx.c_hi, f1 - 1);
+        if (hi >= lo) r_lo = base1 + c2_of(lo), r_hi = base1 + c2_of(hi + 1);
+      } else {
+        const int f2 = 63 - __builtin_clzll(below);
+        below &= ~(1ull << f2);
+        const uint32_t base2 = base1 + c2_of(f2);
+        if (cx.L == P + 2) {
+          const int lo = max(cx.c_lo, 0), hi = min(cx.c_hi, f2 - 1);
+          if (hi >= lo) r_lo = base2 + (uint32_t)lo, r_hi = base2 + (uint32_t)hi + 1;
+        } else {
+          const int f3 = 63 - __builtin_clzll(below);
+          r_lo = base2 + (uint32_t)f3, r_hi = r_lo + 1;
+        }
+      }
+    }
+  }
+  *rlo = r_lo;
+  *rhi = r_hi;
+}
+
 // A node with three spatial columns left (k - 2 points chosen, lowest
 // `low`): its rows go into the table of the oldest node, after that node's
 // triples and records are finished; its triples (within the work unit's
@@ -513,36 +558,8 @@ __device__ __forceinline__ void triple_stage(CX &cx, const St<3> &st, int low) {
   }
   wave_sync_lds();
   // 3. colex ranks of the triples allowed below this node
-  constexpr int P = K - 2; // position of c1 among the candidate's elements
-  uint32_t r_lo = 0, r_hi = 0;
-  {
-    uint64_t below = cx.mask & ((1ull << low) - 1);
-    if (cx.L < P) {
-      r_hi = c3_of(low);
-    } else if (cx.L == P) {
-      const int lo = max(cx.c_lo, 2), hi = min(cx.c_hi, low - 1);
-      if (hi >= lo) r_lo = c3_of(lo), r_hi = c3_of(hi + 1);
-    } else {
-      const int f1 = 63 - __builtin_clzll(below);
-      below &= ~(1ull << f1);
-      const uint32_t base1 = c3_of(f1);
-      if (cx.L == P + 1) {
-        const int lo = max(cx.c_lo, 1), hi = min(cx.c_hi, f1 - 1);
-        if (hi >= lo) r_lo = base1 + c2_of(lo), r_hi = base1 + c2_of(hi + 1);
-      } else {
-        const int f2 = 63 - __builtin_clzll(below);
-        below &= ~(1ull << f2);
-        const uint32_t base2 = base1 + c2_of(f2);
-        if (cx.L == P + 2) {
-          const int lo = max(cx.c_lo, 0), hi = min(cx.c_hi, f2 - 1);
-          if (hi >= lo) r_lo = base2 + (uint32_t)lo, r_hi = base2 + (uint32_t)hi + 1;
-        } else {
-          const int f3 = 63 - __builtin_clzll(below);
-          r_lo = base2 + (uint32_t)f3, r_hi = r_lo + 1;
-        }
-      }
-    }
-  }
+  uint32_t r_lo, r_hi;
+  triple_range<K>(cx, low, &r_lo, &r_hi);
   if constexpr (CX::stats) cx.nodes++;
 #pragma unroll
   for (int i = 0; i + 1 < DENSE_TABLES; i++) cx.nd[i] = cx.nd[i + 1];
@@ -555,6 +572,200 @@ __device__ __forceinline__ void triple_stage(CX &cx, const St<3> &st, int low) {
   }
   // 4. full setup passes over the pending triples of the nodes in flight
   (void)run_setups(cx, 64);
+}
+
+// C(c, 4) for 3 <= c <= 7
+__device__ __forceinline__ uint32_t c4_small(int c) { return c <= 3 ? 0u : c == 4 ? 1u : c == 5 ? 5u : c == 6 ? 15u : 35u; }
+
+// The tail of a node with four spatial columns left (k - 3 points chosen):
+// its children c in [lo_c, hi_c], all below DENSE_TAIL, would be nodes with
+// at most C(6, 3) = 20 triples each.  Their candidates are instead the
+// quadruples {c > c1 > c2 > c3} below DENSE_TAIL (at most C(7, 4) = 35),
+// set up and tested in one pass from this node's rows, with no nodes of
+// their own.  A quadruple's cofactors are the minors of its four rows
+// (s0, s1, s2, s3, h) by three levels of Sylvester's identity, each
+// divided exactly by the node's pivot:
+//     u_j = H0 s0_j - H1 s1_j + H2 s2_j - H3 s3_j + D h_j = prev * M_j,
+// H_a the 4 x 4 minor without column a, D the spatial one; the test is the
+// filter of test_batch with five products, the survivors are decided
+// exactly with lanes as points.
+template <int K, class CX>
+__device__ __forceinline__ void quad_tail(CX &cx, const St<4> &st, int lo_c, int hi_c) {
+  constexpr bool S = CX::stats;
+  const int lane = lane_id();
+  // 1. colex ranks of the quadruples, rank = C(c,4) + C(c1,3) + C(c2,2) + c3
+  uint32_t q_lo, q_hi;
+  if (cx.L <= K - 3) { // c free (or within the unit's sibling run: [lo_c, hi_c] says so)
+    q_lo = c4_small(lo_c);
+    q_hi = c4_small(hi_c + 1);
+  } else { // c fixed by the unit (lo_c == hi_c), the triple below it constrained
+    uint32_t a, b;
+    triple_range<K>(cx, lo_c, &a, &b);
+    q_lo = c4_small(lo_c) + a;
+    q_hi = c4_small(lo_c) + (b > a ? b : a);
+  }
+  if (q_hi <= q_lo) return;
+  if (!charge(cx, 2)) return;
+  const int n = (int)(q_hi - q_lo); // <= 35
+  const int logC = chunk_log(n), C = 1 << logC;
+  const int p = lane >> logC, q = lane & (C - 1);
+  const bool act = p < n;
+  // 2. the node's rows (its heights' shift sig and band as for a table)
+  uint32_t sig = 0;
+  {
+    const int64_t h = ((int64_t)st.H1 << 31) + (int64_t)st.H0;
+    if (ballot(h != (int64_t)(int32_t)h) != 0)
+      sig = wave_umax((uint32_t)(64 - __builtin_clzll((uint64_t)(h ^ (h >> 63)) | 1))) - 31;
+    cx.lds->qS[lane] = make_int4(st.s[0], st.s[1], st.s[2], st.s[3]);
+    cx.lds->qh[lane] = (int32_t)(h >> sig);
+    if (lane < DENSE_TAIL) cx.lds->qx[lane] = make_int2((int32_t)(h >> DENSE_LIMB), (int32_t)(h & DENSE_LMASK));
+  }
+  const uint32_t band = wave_umax((uint32_t)abs(st.s[0]) + (uint32_t)abs(st.s[1]) + (uint32_t)abs(st.s[2]) +
+                                  (uint32_t)abs(st.s[3]));
+  wave_sync_lds();
+  // 3. lanes 2^logC p .. 2^logC p + 2^logC - 1 set up quadruple p (the same
+  //    values in each; an inactive lane takes rank 0 = {3, 2, 1, 0})
+  const uint32_t r = act ? q_lo + (uint32_t)p : 0u;
+  const int c0 = 3 + (r >= 1) + (r >= 5) + (r >= 15);
+  int c1, c2, c3;
+  unrank3(r - c4_small(c0), &c1, &c2, &c3);
+  const int4 A = cx.lds->qS[c0], B = cx.lds->qS[c1], Cr = cx.lds->qS[c2], Dr = cx.lds->qS[c3];
+  const int2 xa = cx.lds->qx[c0], xb = cx.lds->qx[c1], xc = cx.lds->qx[c2], xd = cx.lds->qx[c3];
+  const Div dv = make_div(st.prev);
+  const int32_t a[4] = {A.x, A.y, A.z, A.w}, b[4] = {B.x, B.y, B.z, B.w};
+  const int32_t c[4] = {Cr.x, Cr.y, Cr.z, Cr.w}, dd[4] = {Dr.x, Dr.y, Dr.z, Dr.w};
+  // rows c0, c1: 2 x 2 minors (pairs 01 02 03 12 13 23) and with the height column
+  int32_t m2[6];
+  int64_t m2h[4];
+  {
+    int i = 0;
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+      for (int y = x + 1; y < 4; y++) m2[i++] = exdiv32((int64_t)a[x] * b[y] - (int64_t)a[y] * b[x], dv);
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+      m2h[x] = exdiv_limbs((int64_t)a[x] * xb.x - (int64_t)xa.x * b[x], (int64_t)a[x] * xb.y - (int64_t)xa.y * b[x], dv);
+  }
+  // pair index of {x < y}
+  auto pi = [](int x, int y) { return x == 0 ? y - 1 : x == 1 ? y + 1 : 5; };
+  // rows c0, c1, c2: 3 x 3 minors by expansion along row c2 (signs + - +):
+  // spatial triples 012 013 023 123, and the pairs with the height column
+  int32_t m3[4];
+  int64_t m3h[6];
+  {
+    int i = 0;
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+      for (int y = x + 1; y < 4; y++)
+#pragma unroll
+        for (int z = y + 1; z < 4; z++)
+          m3[i++] = exdiv32((int64_t)c[x] * m2[pi(y, z)] - (int64_t)c[y] * m2[pi(x, z)] + (int64_t)c[z] * m2[pi(x, y)], dv);
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+      for (int y = x + 1; y < 4; y++) {
+        int64_t Hi = (int64_t)xc.x * m2[pi(x, y)], Lo = (int64_t)xc.y * m2[pi(x, y)];
+        acc_limbs(Hi, Lo, c[x], m2h[y]);
+        acc_limbs(Hi, Lo, -c[y], m2h[x]);
+        m3h[pi(x, y)] = exdiv_limbs(Hi, Lo, dv);
+      }
+  }
+  // rows c0..c3: expansion along row c3 (signs - + - +); m3 index of the
+  // spatial triple without column a: 3 - a
+  const int32_t D = exdiv32(-(int64_t)dd[0] * m3[3] + (int64_t)dd[1] * m3[2] - (int64_t)dd[2] * m3[1] +
+                                (int64_t)dd[3] * m3[0], dv);
+  const bool nz = act && D != 0;
+  const bool flip = (D < 0) != (st.prev < 0);
+  int32_t P[4];
+#pragma unroll
+  for (int x = 0; x < 4; x++) P[x] = flip ? -dd[x] : dd[x];
+  const int32_t Ph = flip ? -xd.x : xd.x, Pl = flip ? -xd.y : xd.y;
+  // kappa_a = (-1)^a H_a, H_a over the columns {0..3} \ {a} and h
+  int64_t kap[4];
+#pragma unroll
+  for (int del = 0; del < 4; del++) {
+    int xs[3], m = 0;
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+      if (x != del) xs[m++] = x;
+    const int32_t sgn = (del & 1) ? -1 : 1;
+    int64_t Hi = (int64_t)(sgn * Ph) * m3[3 - del], Lo = (int64_t)(sgn * Pl) * m3[3 - del];
+    acc_limbs(Hi, Lo, -sgn * P[xs[0]], m3h[pi(xs[1], xs[2])]);
+    acc_limbs(Hi, Lo, sgn * P[xs[1]], m3h[pi(xs[0], xs[2])]);
+    acc_limbs(Hi, Lo, -sgn * P[xs[2]], m3h[pi(xs[0], xs[1])]);
+    kap[del] = exdiv_limbs(Hi, Lo, dv);
+  }
+  const int32_t d = flip ? -D : D;
+  // 4. filter test (as in test_batch), 2^logC lanes per quadruple
+  const uint64_t mk = (uint64_t)(kap[0] ^ (kap[0] >> 63)) | (uint64_t)(kap[1] ^ (kap[1] >> 63)) |
+                      (uint64_t)(kap[2] ^ (kap[2] >> 63)) | (uint64_t)(kap[3] ^ (kap[3] >> 63));
+  const int sg = max(max(64 - __builtin_clzll(mk | 1) - 30, 0), (int)sig);
+  const int dl = sg - (int)sig;
+  const int32_t x0 = (int32_t)(kap[0] >> sg), x1 = (int32_t)(kap[1] >> sg), x2 = (int32_t)(kap[2] >> sg),
+                x3 = (int32_t)(kap[3] >> sg);
+  const int64_t bnd = sg > 0 ? (int64_t)band + (d < 0 ? -(int64_t)d : (int64_t)d) - 1 : 0;
+  const int iters = (cx.N + C - 1) >> logC;
+  int32_t neg = 0;
+#pragma unroll 2
+  for (int it = 0; it < iters; it++) {
+    const int j = q + (it << logC);
+    const int4 rw = cx.lds->qS[j];
+    const int32_t hj = cx.lds->qh[j] >> dl;
+    const int64_t v = bnd + (int64_t)rw.x * x0 + (int64_t)rw.y * x1 + (int64_t)rw.z * x2 + (int64_t)rw.w * x3 +
+                      (int64_t)hj * d;
+    neg |= (int32_t)((uint64_t)v >> 32);
+  }
+  const uint64_t rej = ballot(neg < 0);
+  const uint64_t gm = C >= 64 ? ~0ull : ((1ull << C) - 1);
+  uint64_t sm = ballot(nz && q == 0 && ((rej >> (p << logC)) & gm) == 0);
+  if constexpr (S) {
+    cx.setups++;
+    cx.tests++;
+    cx.triples += (uint32_t)n;
+    cx.quads += (uint32_t)n;
+    cx.leaves += (uint32_t)__builtin_popcountll(ballot(nz && q == 0));
+    cx.wide += (uint32_t)__builtin_popcountll(sm);
+  }
+  // 5. survivors: exact, lanes as points with this node's rows in registers
+  if (sm) {
+    const int64_t h = ((int64_t)st.H1 << 31) + (int64_t)st.H0;
+    const int32_t hh = (int32_t)(h >> DENSE_LIMB), hl = (int32_t)(h & DENSE_LMASK);
+    const uint32_t vpack = (uint32_t)c0 | ((uint32_t)c1 << 8) | ((uint32_t)c2 << 16) | ((uint32_t)c3 << 24);
+    while (sm) {
+      const int l = __builtin_ctzll(sm);
+      sm &= sm - 1;
+      int32_t kl[4], kh[4];
+#pragma unroll
+      for (int x = 0; x < 4; x++) {
+        const int64_t kx = (int64_t)(((uint64_t)(uint32_t)rl32((int32_t)((uint64_t)kap[x] >> 32), l) << 32) |
+                                     (uint32_t)rl32((int32_t)(uint32_t)(uint64_t)kap[x], l));
+        kl[x] = (int32_t)(kx & DENSE_LMASK);
+        kh[x] = (int32_t)(kx >> DENSE_LIMB);
+      }
+      const int32_t dl_ = rl32(d, l);
+      const int64_t lo = (int64_t)st.s[0] * kl[0] + (int64_t)st.s[1] * kl[1] + (int64_t)st.s[2] * kl[2] +
+                         (int64_t)st.s[3] * kl[3] + (int64_t)hl * dl_;
+      const int64_t hi = (lo >> DENSE_LIMB) + (int64_t)st.s[0] * kh[0] + (int64_t)st.s[1] * kh[1] +
+                         (int64_t)st.s[2] * kh[2] + (int64_t)st.s[3] * kh[3] + (int64_t)hh * dl_;
+      const bool in = cx.j < cx.N;
+      if (ballot(in && hi < 0)) continue; // a point below within the filter's band
+      const uint64_t zero = ballot(in && hi == 0 && (lo & DENSE_LMASK) == 0);
+      const uint32_t vp = (uint32_t)rl32((int32_t)vpack, l);
+      const uint64_t verts = cx.chosen | (1ull << (vp & 255)) | (1ull << ((vp >> 8) & 255)) |
+                             (1ull << ((vp >> 16) & 255)) | (1ull << (vp >> 24));
+      if (zero != verts) {
+        if (lane == 0) cx.lds->tally.tie = 1;
+        continue;
+      }
+      if (lane == 0) {
+        cx.lds->tally.acc += (unsigned long long)(dl_ < 0 ? -(int64_t)dl_ : (int64_t)dl_);
+        cx.lds->tally.cells += 1;
+      }
+      if constexpr (CX::emit) emit_cell(cx, verts);
+    }
+  }
 }
 
 // End of a work unit: every pending triple and record.
@@ -594,7 +805,9 @@ struct DLevel {
     } else {
       int hi_c, lo_c;
       dense_next_range(cx, T, K, low, &hi_c, &lo_c);
-      for (int c = hi_c; c >= lo_c && step_ok(cx); --c) {
+      // with four columns left, the children below DENSE_TAIL are the tail
+      const int c_end = W == 4 ? max(lo_c, DENSE_TAIL) : lo_c;
+      for (int c = hi_c; c >= c_end && step_ok(cx); --c) {
         int32_t rc[W];
 #pragma unroll
         for (int i = 0; i < W; i++) rc[i] = rl32(st.s[i], c);
@@ -637,6 +850,8 @@ struct DLevel {
         DLevel<K, T + 1, CX>::run(cx, ch, c);
         cx.chosen &= ~(1ull << c);
       }
+      if constexpr (W == 4)
+        if (lo_c < DENSE_TAIL && hi_c >= lo_c) quad_tail<K>(cx, st, lo_c, min(hi_c, DENSE_TAIL - 1));
     }
   }
 };
@@ -700,6 +915,7 @@ __device__ __forceinline__ void dense_commit(CX &cx, const SysDesc &sd, SysAcc *
       atomicAdd((unsigned long long *)&cnt->rsteps, (unsigned long long)cx.setups);
       atomicAdd((unsigned long long *)&cnt->lsteps, (unsigned long long)cx.tests);
       atomicAdd((unsigned long long *)&cnt->triples, (unsigned long long)cx.triples);
+      atomicAdd((unsigned long long *)&cnt->quads, (unsigned long long)cx.quads);
       atomicAdd((unsigned long long *)&cnt->lempty, (unsigned long long)cx.wide);
       atomicAdd((unsigned long long *)&cnt->ridges, (unsigned long long)cx.nodes);
       if (unit) {
@@ -714,7 +930,7 @@ __device__ __forceinline__ void dense_commit(CX &cx, const SysDesc &sd, SysAcc *
     cx.lds->tally.cells = 0;
     cx.lds->tally.tie = 0;
   }
-  cx.inner = cx.sp_upd = cx.pruned = cx.nodes = cx.triples = cx.leaves = cx.setups = cx.tests = cx.wide = 0;
+  cx.inner = cx.sp_upd = cx.pruned = cx.nodes = cx.triples = cx.leaves = cx.setups = cx.tests = cx.wide = cx.quads = 0;
   wave_sync_lds();
 }
 
@@ -779,7 +995,7 @@ dense_kernel(const SysDesc *__restrict__ sys, const int32_t *__restrict__ pts, c
     cx.nd[i].r_cur = cx.nd[i].r_hi = 0;
     cx.nd[i].recs = 0;
   }
-  cx.inner = cx.sp_upd = cx.pruned = cx.nodes = cx.triples = cx.leaves = cx.setups = cx.tests = cx.wide = 0;
+  cx.inner = cx.sp_upd = cx.pruned = cx.nodes = cx.triples = cx.leaves = cx.setups = cx.tests = cx.wide = cx.quads = 0;
   cx.left = 1;
   if (lane == 0) {
     lds->tally.acc = 0;

@@ -31,7 +31,7 @@ __device__ __forceinline__ void clear_counters(DevCounters *cnt) {
   cnt->ridges = cnt->inner = cnt->sp_upd = cnt->pruned = cnt->leaves = cnt->tiles = 0;
   cnt->rsteps = cnt->lsteps = cnt->lempty = 0;
   cnt->w_inner = cnt->w_spatial = cnt->w_ridges = cnt->w_leaves = 0;
-  cnt->triples = cnt->dunits = 0;
+  cnt->triples = cnt->dunits = cnt->quads = 0;
   cnt->next_tile = 0;
   cnt->error = 0;
 }

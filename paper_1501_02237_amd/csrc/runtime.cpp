@@ -272,6 +272,7 @@ int job_collect(Job &job, hipStream_t stream, std::vector<SysAcc> &acc, DevCount
     sum.w_leaves += b.w_leaves;
     sum.triples += b.triples;
     sum.dunits += b.dunits;
+    sum.quads += b.quads;
     sum.error |= b.error;
   }
   if (cnt) *cnt = sum;
