@@ -84,8 +84,12 @@ def ops_per_launch(stats: dict) -> float:
                                    minor, 12; three 3 x 3 height minors in split limbs, 90)
         test per point       19   (eight products, the low limbs' carry shift, the sign accumulation)
     Every node update runs on all N points of its system; a leaf (a
-    candidate with D != 0) tests the N - k - 1 other points; the lane-dense
-    schedule sets up every candidate of its nodes, D = 0 or not.  The counting
+    candidate with D != 0) tests the N - k - 1 other points with lanes as
+    points, and in the lane-dense schedule the points up to its first point
+    proved below (a full test batch stops once every candidate has one), as
+    counted by the counting variant; the lane-dense schedule sets up every
+    candidate of its nodes, D = 0 or not (tail quadruples at the rate of a
+    triple).  The counting
     kernel variant reports the counts already weighted by each system's N
     (exact for batches of mixed sizes): a ridge adds one spatial and one
     height entry per point, an inner node one height entry and W - 1 spatial

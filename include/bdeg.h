@@ -103,7 +103,10 @@ typedef struct {
   uint64_t point_inner;       /* sum of N * inner_nodes */
   uint64_t point_spatial;     /* sum of N * spatial_updates */
   uint64_t point_ridges;      /* sum of N * ridges */
-  uint64_t leaf_points;       /* sum of (N - k - 1) * leaves: points tested by the leaf tests */
+  uint64_t leaf_points;       /* points the leaf tests examined: (N - k - 1) per leaf with lanes
+                                 as points; in the lane-dense kernel, per candidate, the points up to
+                                 its first point proved below (its test batch may stop there), or
+                                 N - k - 1 */
   /* lane-dense schedule (BDEG_SCHED_AUTO): it creates no ridges; there
      `ridges` counts its nodes with three spatial columns left, `leaves` the
      candidates with D != 0 it tested, ridge_steps its setup passes,

@@ -120,6 +120,7 @@ struct DCtx {
   int head, nrec;  // record ring: first record and count (wave-uniform)
   int32_t left;    // watchdog budget (as in enum_device.hpp)
   uint32_t inner, sp_upd, pruned, nodes, triples, leaves, setups, tests, wide, quads;
+  uint32_t lpts; // per lane: points examined by its candidates' tests (counting variant)
   CellSink sink;
 };
 
@@ -137,27 +138,28 @@ __device__ __forceinline__ int64_t exdiv_limbs(int64_t Hi, int64_t Lo, const Div
 }
 
 // Colex unranking of a 3-subset {c1 > c2 > c3}: rank = C(c1,3) + C(c2,2) + c3.
-// Compares 6 r with c (c-1) (c-2) (no division); r < C(64, 3).
+// Compares 6 r with c (c-1) (c-2) (no division); r < C(64, 3).  No bound
+// tests are needed: c1 = 64 (or 65) already fails, as 6 r < 64 * 63 * 62,
+// and c2 >= c1 fails, as the remainder is below C(c1, 2); so each step is a
+// compare and a select.
 __device__ __forceinline__ void unrank3(uint32_t r, int *c1, int *c2, int *c3) {
   const uint32_t r6 = 6u * r;
   uint32_t a = 2;
 #pragma unroll
   for (uint32_t step = 32; step >= 1; step >>= 1) {
     const uint32_t x = a + step;
-    const uint32_t p = __umul24(__umul24(x, x - 1), x - 2);
-    if (x <= 63 && p <= r6) a = x;
+    a = __umul24(__umul24(x, x - 1), x - 2) <= r6 ? x : a;
   }
-  const uint32_t rem6 = r6 - __umul24(__umul24(a, a - 1), a - 2); // 6 (C(c2,2) + c3)
+  const uint32_t rem2 = (r6 - __umul24(__umul24(a, a - 1), a - 2)) / 3u; // 2 (C(c2,2) + c3)
   uint32_t b = 1;
 #pragma unroll
   for (uint32_t step = 32; step >= 1; step >>= 1) {
     const uint32_t x = b + step;
-    if (x < a && 3u * __umul24(x, x - 1) <= rem6) b = x;
+    b = __umul24(x, x - 1) <= rem2 ? x : b;
   }
-  const uint32_t c6 = rem6 - 3u * __umul24(b, b - 1); // 6 c3, c3 < 64
   *c1 = (int)a;
   *c2 = (int)b;
-  *c3 = (int)((c6 * 10923u) >> 16);
+  *c3 = (int)((rem2 - __umul24(b, b - 1)) >> 1);
 }
 
 __device__ __forceinline__ uint32_t c3_of(int c) { return (uint32_t)(c * (c - 1) * (c - 2) / 6); }
@@ -183,6 +185,17 @@ __device__ __forceinline__ int rec_shift(const int32_t *rc) { return (int)((uint
 __device__ __forceinline__ int32_t limb_shift(int32_t kl, int32_t kh, int sg) {
   return sg >= DENSE_LIMB ? (kh >> (sg - DENSE_LIMB))
                           : (int32_t)(((uint32_t)kh << (DENSE_LIMB - sg)) + ((uint32_t)kl >> sg));
+}
+
+// Wave-wide sum (every lane active), as wave_umax below.
+__device__ __forceinline__ uint32_t wave_usum(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false); // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false); // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false); // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false); // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false); // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false); // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // Wave-wide maximum of an unsigned value (every lane active): a row-wise DPP
@@ -243,6 +256,26 @@ __device__ __forceinline__ void decide_exact(CX &cx, const int32_t *rc, int t) {
   if constexpr (CX::emit) emit_cell(cx, verts);
 }
 
+// The points of a full test batch (one candidate per lane) until every
+// valid lane has a point proved below (neg < 0), checked every four points.
+// (The counting variant also records, per lane, how many points its
+// candidate needed: up to its first point proved below.)
+template <bool SHIFT, bool STATS>
+__device__ __forceinline__ void test_points_early(const int4 *rowS, int iters, bool valid, int32_t x0, int32_t x1,
+                                                  int32_t x2, int32_t d, int64_t bnd, int dl, int32_t &neg,
+                                                  int32_t &first) {
+#pragma unroll 4
+  for (int j = 0; j < iters; j++) {
+    const int4 r = rowS[j];
+    const int32_t hj = SHIFT ? (r.w >> dl) : r.w;
+    const int64_t v = bnd + (int64_t)r.x * x0 + (int64_t)r.y * x1 + (int64_t)r.z * x2 + (int64_t)hj * d;
+    neg |= (int32_t)((uint64_t)v >> 32);
+    if constexpr (STATS)
+      if (first == 0 && neg < 0) first = j + 1;
+    if ((j & 3) == 3 && ballot(valid && neg >= 0) == 0) break;
+  }
+}
+
 // Test the n oldest records of the ring (n <= 64), each over all points, its
 // points split over 2^logC lanes.
 template <class CX>
@@ -277,8 +310,15 @@ __device__ __forceinline__ void test_batch(CX &cx, int n, int logC) {
   const int32_t d = rc[6];
   const int64_t bnd = sg > 0 ? (int64_t)sb.y + (d < 0 ? -(int64_t)d : (int64_t)d) - 1 : 0;
   const int4 *rowS = cx.lds->rowS[t];
-  int32_t neg = 0;
-  if (ballot(valid && dl != 0) == 0) {
+  int32_t neg = 0, first = 0;
+  const bool shifted = ballot(valid && dl != 0) != 0;
+  if (logC == 0) {
+    // a full batch stops once every candidate has a point proved below
+    if (!shifted)
+      test_points_early<false, CX::stats>(rowS, iters, valid, x0, x1, x2, d, bnd, 0, neg, first);
+    else
+      test_points_early<true, CX::stats>(rowS, iters, valid, x0, x1, x2, d, bnd, dl, neg, first);
+  } else if (!shifted) {
 #pragma unroll 4
     for (int it = 0; it < iters; it++) {
       const int j = q + (it << logC); // < 64: 2^logC divides 64 and N <= 64
@@ -295,7 +335,12 @@ __device__ __forceinline__ void test_batch(CX &cx, int n, int logC) {
       neg |= (int32_t)((uint64_t)v >> 32);
     }
   }
-  if constexpr (CX::stats) cx.tests++;
+  if constexpr (CX::stats) {
+    cx.tests++;
+    // points examined: up to the first point proved below (full batches),
+    // else every other point
+    if (valid && q == 0) cx.lpts += (uint32_t)((logC == 0 && first > 0) ? first : cx.N - cx.k - 1);
+  }
   const uint64_t rej = ballot(neg < 0);
   const int C = 1 << logC;
   const uint64_t gm = C >= 64 ? ~0ull : ((1ull << C) - 1);
@@ -707,8 +752,8 @@ __device__ __forceinline__ void quad_tail(CX &cx, const St<4> &st, int lo_c, int
                 x3 = (int32_t)(kap[3] >> sg);
   const int64_t bnd = sg > 0 ? (int64_t)band + (d < 0 ? -(int64_t)d : (int64_t)d) - 1 : 0;
   const int iters = (cx.N + C - 1) >> logC;
-  int32_t neg = 0;
-#pragma unroll 2
+  int32_t neg = 0, first = 0;
+#pragma unroll 4
   for (int it = 0; it < iters; it++) {
     const int j = q + (it << logC);
     const int4 rw = cx.lds->qS[j];
@@ -716,6 +761,10 @@ __device__ __forceinline__ void quad_tail(CX &cx, const St<4> &st, int lo_c, int
     const int64_t v = bnd + (int64_t)rw.x * x0 + (int64_t)rw.y * x1 + (int64_t)rw.z * x2 + (int64_t)rw.w * x3 +
                       (int64_t)hj * d;
     neg |= (int32_t)((uint64_t)v >> 32);
+    if constexpr (S)
+      if (first == 0 && neg < 0) first = it + 1;
+    // one quadruple per lane: stop once each has a point proved below
+    if (logC == 0 && (it & 3) == 3 && ballot(act && neg >= 0) == 0) break;
   }
   const uint64_t rej = ballot(neg < 0);
   const uint64_t gm = C >= 64 ? ~0ull : ((1ull << C) - 1);
@@ -727,6 +776,7 @@ __device__ __forceinline__ void quad_tail(CX &cx, const St<4> &st, int lo_c, int
     cx.quads += (uint32_t)n;
     cx.leaves += (uint32_t)__builtin_popcountll(ballot(nz && q == 0));
     cx.wide += (uint32_t)__builtin_popcountll(sm);
+    if (nz && q == 0) cx.lpts += (uint32_t)((logC == 0 && first > 0) ? first : cx.N - cx.k - 1);
   }
   // 5. survivors: exact, lanes as points with this node's rows in registers
   if (sm) {
@@ -890,6 +940,8 @@ template <class CX>
 __device__ __forceinline__ void dense_commit(CX &cx, const SysDesc &sd, SysAcc *a, DevCounters *cnt, bool unit) {
   constexpr bool S = CX::stats;
   const int lane = lane_id();
+  uint32_t lpts = 0;
+  if constexpr (S) lpts = wave_usum(cx.lpts);
   wave_sync_lds();
   const bool abandoned = cx.left <= 0;
   if (lane == 0 && abandoned) atomicOr(&cnt->error, 1u);
@@ -903,7 +955,7 @@ __device__ __forceinline__ void dense_commit(CX &cx, const SysDesc &sd, SysAcc *
       if (tie) atomicOr(&a->tie, 1u);
     }
     if constexpr (S) {
-      const unsigned long long n = (unsigned long long)sd.N, t = (unsigned long long)(sd.N - sd.k - 1);
+      const unsigned long long n = (unsigned long long)sd.N;
       atomicAdd((unsigned long long *)&cnt->inner, (unsigned long long)cx.inner);
       atomicAdd((unsigned long long *)&cnt->sp_upd, (unsigned long long)cx.sp_upd);
       atomicAdd((unsigned long long *)&cnt->pruned, (unsigned long long)cx.pruned);
@@ -924,13 +976,13 @@ __device__ __forceinline__ void dense_commit(CX &cx, const SysDesc &sd, SysAcc *
       }
       atomicAdd((unsigned long long *)&cnt->w_inner, n * cx.inner);
       atomicAdd((unsigned long long *)&cnt->w_spatial, n * cx.sp_upd);
-      atomicAdd((unsigned long long *)&cnt->w_leaves, t * cx.leaves);
+      atomicAdd((unsigned long long *)&cnt->w_leaves, (unsigned long long)lpts);
     }
     cx.lds->tally.acc = 0;
     cx.lds->tally.cells = 0;
     cx.lds->tally.tie = 0;
   }
-  cx.inner = cx.sp_upd = cx.pruned = cx.nodes = cx.triples = cx.leaves = cx.setups = cx.tests = cx.wide = cx.quads = 0;
+  cx.inner = cx.sp_upd = cx.pruned = cx.nodes = cx.triples = cx.leaves = cx.setups = cx.tests = cx.wide = cx.quads = cx.lpts = 0;
   wave_sync_lds();
 }
 
@@ -995,7 +1047,7 @@ dense_kernel(const SysDesc *__restrict__ sys, const int32_t *__restrict__ pts, c
     cx.nd[i].r_cur = cx.nd[i].r_hi = 0;
     cx.nd[i].recs = 0;
   }
-  cx.inner = cx.sp_upd = cx.pruned = cx.nodes = cx.triples = cx.leaves = cx.setups = cx.tests = cx.wide = cx.quads = 0;
+  cx.inner = cx.sp_upd = cx.pruned = cx.nodes = cx.triples = cx.leaves = cx.setups = cx.tests = cx.wide = cx.quads = cx.lpts = 0;
   cx.left = 1;
   if (lane == 0) {
     lds->tally.acc = 0;
