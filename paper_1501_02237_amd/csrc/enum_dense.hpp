@@ -619,6 +619,81 @@ __device__ __forceinline__ void triple_stage(CX &cx, const St<3> &st, int low) {
   (void)run_setups(cx, 64);
 }
 
+// Cofactors of the tail quadruple {c0 > c1 > c2 > c3} from the rows in the
+// tail table (all three levels divided exactly by the node's pivot): D, the
+// spatial 4 x 4 minor, and kap_a = (-1)^a H_a, with row c3 taken times
+// sign(D) sign(pivot) (so that a lower facet has every u_j > 0); d is D times
+// the same sign.
+__device__ __forceinline__ void quad_cofactors(const DenseLds *L, int c0, int c1, int c2, int c3, const Div &dv,
+                                               bool prevneg, int64_t kap[4], int32_t &D, int32_t &d) {
+  const int4 A = L->qS[c0], B = L->qS[c1], Cr = L->qS[c2], Dr = L->qS[c3];
+  const int2 xa = L->qx[c0], xb = L->qx[c1], xc = L->qx[c2], xd = L->qx[c3];
+  const int32_t a[4] = {A.x, A.y, A.z, A.w}, b[4] = {B.x, B.y, B.z, B.w};
+  const int32_t c[4] = {Cr.x, Cr.y, Cr.z, Cr.w}, dd[4] = {Dr.x, Dr.y, Dr.z, Dr.w};
+  // rows c0, c1: 2 x 2 minors (pairs 01 02 03 12 13 23) and with the height column
+  int32_t m2[6];
+  int64_t m2h[4];
+  {
+    int i = 0;
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+      for (int y = x + 1; y < 4; y++) m2[i++] = exdiv32((int64_t)a[x] * b[y] - (int64_t)a[y] * b[x], dv);
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+      m2h[x] = exdiv_limbs((int64_t)a[x] * xb.x - (int64_t)xa.x * b[x], (int64_t)a[x] * xb.y - (int64_t)xa.y * b[x], dv);
+  }
+  // pair index of {x < y}
+  auto pi = [](int x, int y) { return x == 0 ? y - 1 : x == 1 ? y + 1 : 5; };
+  // rows c0, c1, c2: 3 x 3 minors by expansion along row c2 (signs + - +):
+  // spatial triples 012 013 023 123, and the pairs with the height column
+  int32_t m3[4];
+  int64_t m3h[6];
+  {
+    int i = 0;
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+      for (int y = x + 1; y < 4; y++)
+#pragma unroll
+        for (int z = y + 1; z < 4; z++)
+          m3[i++] = exdiv32((int64_t)c[x] * m2[pi(y, z)] - (int64_t)c[y] * m2[pi(x, z)] + (int64_t)c[z] * m2[pi(x, y)], dv);
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+      for (int y = x + 1; y < 4; y++) {
+        int64_t Hi = (int64_t)xc.x * m2[pi(x, y)], Lo = (int64_t)xc.y * m2[pi(x, y)];
+        acc_limbs(Hi, Lo, c[x], m2h[y]);
+        acc_limbs(Hi, Lo, -c[y], m2h[x]);
+        m3h[pi(x, y)] = exdiv_limbs(Hi, Lo, dv);
+      }
+  }
+  // rows c0..c3: expansion along row c3 (signs - + - +); m3 index of the
+  // spatial triple without column a: 3 - a
+  D = exdiv32(-(int64_t)dd[0] * m3[3] + (int64_t)dd[1] * m3[2] - (int64_t)dd[2] * m3[1] + (int64_t)dd[3] * m3[0],
+              dv);
+  const bool flip = (D < 0) != prevneg;
+  int32_t P[4];
+#pragma unroll
+  for (int x = 0; x < 4; x++) P[x] = flip ? -dd[x] : dd[x];
+  const int32_t Ph = flip ? -xd.x : xd.x, Pl = flip ? -xd.y : xd.y;
+  // kappa_a = (-1)^a H_a, H_a over the columns {0..3} \ {a} and h
+#pragma unroll
+  for (int del = 0; del < 4; del++) {
+    int xs[3], m = 0;
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+      if (x != del) xs[m++] = x;
+    const int32_t sgn = (del & 1) ? -1 : 1;
+    int64_t Hi = (int64_t)(sgn * Ph) * m3[3 - del], Lo = (int64_t)(sgn * Pl) * m3[3 - del];
+    acc_limbs(Hi, Lo, -sgn * P[xs[0]], m3h[pi(xs[1], xs[2])]);
+    acc_limbs(Hi, Lo, sgn * P[xs[1]], m3h[pi(xs[0], xs[2])]);
+    acc_limbs(Hi, Lo, -sgn * P[xs[2]], m3h[pi(xs[0], xs[1])]);
+    kap[del] = exdiv_limbs(Hi, Lo, dv);
+  }
+  d = flip ? -D : D;
+}
+
 // C(c, 4) for 3 <= c <= 7
 __device__ __forceinline__ uint32_t c4_small(int c) { return c <= 3 ? 0u : c == 4 ? 1u : c == 5 ? 5u : c == 6 ? 15u : 35u; }
 
@@ -674,75 +749,11 @@ __device__ __forceinline__ void quad_tail(CX &cx, const St<4> &st, int lo_c, int
   const int c0 = 3 + (r >= 1) + (r >= 5) + (r >= 15);
   int c1, c2, c3;
   unrank3(r - c4_small(c0), &c1, &c2, &c3);
-  const int4 A = cx.lds->qS[c0], B = cx.lds->qS[c1], Cr = cx.lds->qS[c2], Dr = cx.lds->qS[c3];
-  const int2 xa = cx.lds->qx[c0], xb = cx.lds->qx[c1], xc = cx.lds->qx[c2], xd = cx.lds->qx[c3];
   const Div dv = make_div(st.prev);
-  const int32_t a[4] = {A.x, A.y, A.z, A.w}, b[4] = {B.x, B.y, B.z, B.w};
-  const int32_t c[4] = {Cr.x, Cr.y, Cr.z, Cr.w}, dd[4] = {Dr.x, Dr.y, Dr.z, Dr.w};
-  // rows c0, c1: 2 x 2 minors (pairs 01 02 03 12 13 23) and with the height column
-  int32_t m2[6];
-  int64_t m2h[4];
-  {
-    int i = 0;
-#pragma unroll
-    for (int x = 0; x < 4; x++)
-#pragma unroll
-      for (int y = x + 1; y < 4; y++) m2[i++] = exdiv32((int64_t)a[x] * b[y] - (int64_t)a[y] * b[x], dv);
-#pragma unroll
-    for (int x = 0; x < 4; x++)
-      m2h[x] = exdiv_limbs((int64_t)a[x] * xb.x - (int64_t)xa.x * b[x], (int64_t)a[x] * xb.y - (int64_t)xa.y * b[x], dv);
-  }
-  // pair index of {x < y}
-  auto pi = [](int x, int y) { return x == 0 ? y - 1 : x == 1 ? y + 1 : 5; };
-  // rows c0, c1, c2: 3 x 3 minors by expansion along row c2 (signs + - +):
-  // spatial triples 012 013 023 123, and the pairs with the height column
-  int32_t m3[4];
-  int64_t m3h[6];
-  {
-    int i = 0;
-#pragma unroll
-    for (int x = 0; x < 4; x++)
-#pragma unroll
-      for (int y = x + 1; y < 4; y++)
-#pragma unroll
-        for (int z = y + 1; z < 4; z++)
-          m3[i++] = exdiv32((int64_t)c[x] * m2[pi(y, z)] - (int64_t)c[y] * m2[pi(x, z)] + (int64_t)c[z] * m2[pi(x, y)], dv);
-#pragma unroll
-    for (int x = 0; x < 4; x++)
-#pragma unroll
-      for (int y = x + 1; y < 4; y++) {
-        int64_t Hi = (int64_t)xc.x * m2[pi(x, y)], Lo = (int64_t)xc.y * m2[pi(x, y)];
-        acc_limbs(Hi, Lo, c[x], m2h[y]);
-        acc_limbs(Hi, Lo, -c[y], m2h[x]);
-        m3h[pi(x, y)] = exdiv_limbs(Hi, Lo, dv);
-      }
-  }
-  // rows c0..c3: expansion along row c3 (signs - + - +); m3 index of the
-  // spatial triple without column a: 3 - a
-  const int32_t D = exdiv32(-(int64_t)dd[0] * m3[3] + (int64_t)dd[1] * m3[2] - (int64_t)dd[2] * m3[1] +
-                                (int64_t)dd[3] * m3[0], dv);
-  const bool nz = act && D != 0;
-  const bool flip = (D < 0) != (st.prev < 0);
-  int32_t P[4];
-#pragma unroll
-  for (int x = 0; x < 4; x++) P[x] = flip ? -dd[x] : dd[x];
-  const int32_t Ph = flip ? -xd.x : xd.x, Pl = flip ? -xd.y : xd.y;
-  // kappa_a = (-1)^a H_a, H_a over the columns {0..3} \ {a} and h
   int64_t kap[4];
-#pragma unroll
-  for (int del = 0; del < 4; del++) {
-    int xs[3], m = 0;
-#pragma unroll
-    for (int x = 0; x < 4; x++)
-      if (x != del) xs[m++] = x;
-    const int32_t sgn = (del & 1) ? -1 : 1;
-    int64_t Hi = (int64_t)(sgn * Ph) * m3[3 - del], Lo = (int64_t)(sgn * Pl) * m3[3 - del];
-    acc_limbs(Hi, Lo, -sgn * P[xs[0]], m3h[pi(xs[1], xs[2])]);
-    acc_limbs(Hi, Lo, sgn * P[xs[1]], m3h[pi(xs[0], xs[2])]);
-    acc_limbs(Hi, Lo, -sgn * P[xs[2]], m3h[pi(xs[0], xs[1])]);
-    kap[del] = exdiv_limbs(Hi, Lo, dv);
-  }
-  const int32_t d = flip ? -D : D;
+  int32_t D, d;
+  quad_cofactors(cx.lds, c0, c1, c2, c3, dv, st.prev < 0, kap, D, d);
+  const bool nz = act && D != 0;
   // 4. filter test (as in test_batch), 2^logC lanes per quadruple
   const uint64_t mk = (uint64_t)(kap[0] ^ (kap[0] >> 63)) | (uint64_t)(kap[1] ^ (kap[1] >> 63)) |
                       (uint64_t)(kap[2] ^ (kap[2] >> 63)) | (uint64_t)(kap[3] ^ (kap[3] >> 63));
@@ -752,19 +763,43 @@ __device__ __forceinline__ void quad_tail(CX &cx, const St<4> &st, int lo_c, int
                 x3 = (int32_t)(kap[3] >> sg);
   const int64_t bnd = sg > 0 ? (int64_t)band + (d < 0 ? -(int64_t)d : (int64_t)d) - 1 : 0;
   const int iters = (cx.N + C - 1) >> logC;
+  // Blocks of four points; the next block's rows are read before this
+  // block's sums, so that the reads overlap the arithmetic.  Points past
+  // the block count are zero rows or repeat row 63: harmless.
   int32_t neg = 0, first = 0;
-#pragma unroll 4
-  for (int it = 0; it < iters; it++) {
-    const int j = q + (it << logC);
-    const int4 rw = cx.lds->qS[j];
-    const int32_t hj = cx.lds->qh[j] >> dl;
-    const int64_t v = bnd + (int64_t)rw.x * x0 + (int64_t)rw.y * x1 + (int64_t)rw.z * x2 + (int64_t)rw.w * x3 +
-                      (int64_t)hj * d;
-    neg |= (int32_t)((uint64_t)v >> 32);
-    if constexpr (S)
-      if (first == 0 && neg < 0) first = it + 1;
-    // one quadruple per lane: stop once each has a point proved below
-    if (logC == 0 && (it & 3) == 3 && ballot(act && neg >= 0) == 0) break;
+  int4 cr[4];
+  int32_t chh[4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const int j = min(q + (u << logC), 63);
+    cr[u] = cx.lds->qS[j];
+    chh[u] = cx.lds->qh[j];
+  }
+  for (int it0 = 0; it0 < iters; it0 += 4) {
+    int4 nr[4];
+    int32_t nh[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int j = min(q + ((it0 + 4 + u) << logC), 63);
+      nr[u] = cx.lds->qS[j];
+      nh[u] = cx.lds->qh[j];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int32_t hj = chh[u] >> dl;
+      const int64_t v = bnd + (int64_t)cr[u].x * x0 + (int64_t)cr[u].y * x1 + (int64_t)cr[u].z * x2 +
+                        (int64_t)cr[u].w * x3 + (int64_t)hj * d;
+      neg |= (int32_t)((uint64_t)v >> 32);
+      if constexpr (S)
+        if (first == 0 && neg < 0) first = it0 + u + 1;
+    }
+    // one quadruple per lane: stop once each (with D != 0) has a point proved below
+    if (logC == 0 && ballot(nz && neg >= 0) == 0) break;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      cr[u] = nr[u];
+      chh[u] = nh[u];
+    }
   }
   const uint64_t rej = ballot(neg < 0);
   const uint64_t gm = C >= 64 ? ~0ull : ((1ull << C) - 1);
@@ -786,15 +821,19 @@ __device__ __forceinline__ void quad_tail(CX &cx, const St<4> &st, int lo_c, int
     while (sm) {
       const int l = __builtin_ctzll(sm);
       sm &= sm - 1;
+      // (the exact cofactors again, for this one quadruple: rarely needed,
+      // so not kept in registers through the test)
+      const uint32_t vp = (uint32_t)rl32((int32_t)vpack, l);
+      int64_t kx[4];
+      int32_t Dx, dl_;
+      quad_cofactors(cx.lds, (int)(vp & 255), (int)((vp >> 8) & 255), (int)((vp >> 16) & 255), (int)(vp >> 24), dv,
+                     st.prev < 0, kx, Dx, dl_);
       int32_t kl[4], kh[4];
 #pragma unroll
       for (int x = 0; x < 4; x++) {
-        const int64_t kx = (int64_t)(((uint64_t)(uint32_t)rl32((int32_t)((uint64_t)kap[x] >> 32), l) << 32) |
-                                     (uint32_t)rl32((int32_t)(uint32_t)(uint64_t)kap[x], l));
-        kl[x] = (int32_t)(kx & DENSE_LMASK);
-        kh[x] = (int32_t)(kx >> DENSE_LIMB);
+        kl[x] = (int32_t)(kx[x] & DENSE_LMASK);
+        kh[x] = (int32_t)(kx[x] >> DENSE_LIMB);
       }
-      const int32_t dl_ = rl32(d, l);
       const int64_t lo = (int64_t)st.s[0] * kl[0] + (int64_t)st.s[1] * kl[1] + (int64_t)st.s[2] * kl[2] +
                          (int64_t)st.s[3] * kl[3] + (int64_t)hl * dl_;
       const int64_t hi = (lo >> DENSE_LIMB) + (int64_t)st.s[0] * kh[0] + (int64_t)st.s[1] * kh[1] +
@@ -802,7 +841,6 @@ __device__ __forceinline__ void quad_tail(CX &cx, const St<4> &st, int lo_c, int
       const bool in = cx.j < cx.N;
       if (ballot(in && hi < 0)) continue; // a point below within the filter's band
       const uint64_t zero = ballot(in && hi == 0 && (lo & DENSE_LMASK) == 0);
-      const uint32_t vp = (uint32_t)rl32((int32_t)vpack, l);
       const uint64_t verts = cx.chosen | (1ull << (vp & 255)) | (1ull << ((vp >> 8) & 255)) |
                              (1ull << ((vp >> 16) & 255)) | (1ull << (vp >> 24));
       if (zero != verts) {
