@@ -84,7 +84,8 @@ constexpr uint32_t BAND_UNSET = 0xFFFFFFFFu;
 struct alignas(16) DenseLds {
   int4 rowS[DENSE_TABLES][64];            // s0, s1, s2, h >> sig
   int2 rowH[DENSE_TABLES][64];            // h split at bit 29: hh, hl
-  alignas(16) int32_t rec[DENSE_RING][8]; // kl0, kh0, kl1, kh1, kl2, kh2, d, vertices | table | shift
+  int4 recX[DENSE_RING];    // a candidate's filter coefficients k0 >> sg, k1 >> sg, k2 >> sg and d
+  int32_t recM[DENSE_RING]; // c1 | c2 << 8 | c3 << 16 | table | shift sg
   TableInfo info[DENSE_TABLES];
   // rows of the node whose tail quadruples are set up (four spatial columns)
   int4 qS[64];  // s0, s1, s2, s3
@@ -171,21 +172,13 @@ __device__ __forceinline__ void acc_limbs(int64_t &Hi, int64_t &Lo, int32_t a, i
   Lo += (int64_t)a * (int32_t)(M & DENSE_LMASK);
 }
 
-// A candidate record: its coefficients split at bit 29 (k = kh 2^29 + kl,
-// 0 <= kl < 2^29) as kl0, kh0, kl1, kh1, kl2, kh2, then d, then
-// c1 | c2 << 8 | c3 << 16, its node table in the two bits at REC_TABLE_BIT
-// and the shift of its filter test (below) in the five bits at REC_SHIFT_BIT.
+// A candidate record holds what its filter test needs: k_a >> sg (a = 0, 1,
+// 2) and d, and a word with c1 | c2 << 8 | c3 << 16, its node table in the
+// two bits at REC_TABLE_BIT and the shift sg in the five bits at
+// REC_SHIFT_BIT.  The exact cofactors of the rare candidates the filter
+// cannot reject are derived again from the table.
 constexpr int REC_TABLE_BIT = 25;
 constexpr int REC_SHIFT_BIT = 27;
-__device__ __forceinline__ int rec_table(const int32_t *rc) { return (rc[7] >> REC_TABLE_BIT) & 3; }
-__device__ __forceinline__ int rec_shift(const int32_t *rc) { return (int)((uint32_t)rc[7] >> REC_SHIFT_BIT); }
-
-// floor((kh 2^29 + kl) / 2^sg), 0 <= kl < 2^29, for a quotient that fits
-// int32 (sg <= 31): for sg < 29 the wrapping sum has the quotient's bits.
-__device__ __forceinline__ int32_t limb_shift(int32_t kl, int32_t kh, int sg) {
-  return sg >= DENSE_LIMB ? (kh >> (sg - DENSE_LIMB))
-                          : (int32_t)(((uint32_t)kh << (DENSE_LIMB - sg)) + ((uint32_t)kl >> sg));
-}
 
 // Wave-wide sum (every lane active), as wave_umax below.
 __device__ __forceinline__ uint32_t wave_usum(uint32_t v) {
@@ -212,43 +205,86 @@ __device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
 
 
 
-// u_j = k0 s0 + k1 s1 + k2 s2 + d h exactly, as (hi, lo) with
-// u = 2^29 hi + (lo mod 2^29): every product is a 32 x 32 -> 64 multiply-add
-// (|s|, |d| < 2^30; |k|, |h| < 2^59), the low limbs sum below 2^61 and the
-// high limbs below 2^62.
-struct UVal {
-  int64_t hi, lo;
-};
-__device__ __forceinline__ UVal u_exact(const int32_t *rc, int32_t s0, int32_t s1, int32_t s2, int32_t hh,
-                                        int32_t hl) {
-  const int64_t lo = (int64_t)s0 * rc[0] + (int64_t)s1 * rc[2] + (int64_t)s2 * rc[4] + (int64_t)hl * rc[6];
-  UVal u;
-  u.hi = (lo >> DENSE_LIMB) + (int64_t)s0 * rc[1] + (int64_t)s1 * rc[3] + (int64_t)s2 * rc[5] + (int64_t)hh * rc[6];
-  u.lo = lo;
-  return u;
+// Cofactors of the triple {c1 > c2 > c3} of the node in row table t, from
+// its rows (heights split at bit 29: h = hh 2^29 + l, 0 <= l < 2^29) and its
+// pivot data: the 2 x 2 minors of rows c1, c2 (T+2 minors), spatial and
+// with the height column; then the 3 x 3 minors of rows c1, c2, c3 (T+3
+// minors) by expansion along row c3: the spatial one D first, then, with
+// row c3 multiplied by the orientation sign(D) sign(prev) (every minor
+// below is linear in it), the coefficients of u_j: k0 = -H0, k1 = H1,
+// k2 = -H2 (H_a: column a deleted); d is D times the same sign.
+__device__ __forceinline__ void triple_cofactors(const DenseLds *L, int t, int c1, int c2, int c3, const Div &dv,
+                                                 bool prevneg, int64_t &k0, int64_t &k1, int64_t &k2, int32_t &D,
+                                                 int32_t &d) {
+  const int4 *RS = L->rowS[t];
+  const int2 *RH = L->rowH[t];
+  const int4 a1 = RS[c1], a2 = RS[c2], a3 = RS[c3];
+  const int2 x1 = RH[c1], x2 = RH[c2], x3 = RH[c3];
+  const int32_t hh1 = x1.x, l1 = x1.y, hh2 = x2.x, l2 = x2.y, hh3 = x3.x, l3 = x3.y;
+  const int32_t s01 = a1.x, s11 = a1.y, s21 = a1.z;
+  const int32_t s02 = a2.x, s12 = a2.y, s22 = a2.z;
+  const int32_t s03 = a3.x, s13 = a3.y, s23 = a3.z;
+  const int32_t m01 = exdiv32((int64_t)s01 * s12 - (int64_t)s11 * s02, dv);
+  const int32_t m02 = exdiv32((int64_t)s01 * s22 - (int64_t)s21 * s02, dv);
+  const int32_t m12 = exdiv32((int64_t)s11 * s22 - (int64_t)s21 * s12, dv);
+  const int64_t m0h = exdiv_limbs((int64_t)s01 * hh2 - (int64_t)hh1 * s02, (int64_t)s01 * l2 - (int64_t)l1 * s02, dv);
+  const int64_t m1h = exdiv_limbs((int64_t)s11 * hh2 - (int64_t)hh1 * s12, (int64_t)s11 * l2 - (int64_t)l1 * s12, dv);
+  const int64_t m2h = exdiv_limbs((int64_t)s21 * hh2 - (int64_t)hh1 * s22, (int64_t)s21 * l2 - (int64_t)l1 * s22, dv);
+  D = exdiv32((int64_t)s03 * m12 - (int64_t)s13 * m02 + (int64_t)s23 * m01, dv);
+  const bool flip = (D < 0) != prevneg;
+  const int32_t P0 = flip ? -s03 : s03, P1 = flip ? -s13 : s13, P2 = flip ? -s23 : s23;
+  const int32_t Ph = flip ? -hh3 : hh3, Pl = flip ? -l3 : l3;
+  int64_t Hi, Lo;
+  Hi = (int64_t)(-Ph) * m12, Lo = (int64_t)(-Pl) * m12;
+  acc_limbs(Hi, Lo, -P1, m2h);
+  acc_limbs(Hi, Lo, P2, m1h);
+  k0 = exdiv_limbs(Hi, Lo, dv); // -H0, columns s1, s2, h
+  Hi = (int64_t)Ph * m02, Lo = (int64_t)Pl * m02;
+  acc_limbs(Hi, Lo, P0, m2h);
+  acc_limbs(Hi, Lo, -P2, m0h);
+  k1 = exdiv_limbs(Hi, Lo, dv); // H1, columns s0, s2, h
+  Hi = (int64_t)(-Ph) * m01, Lo = (int64_t)(-Pl) * m01;
+  acc_limbs(Hi, Lo, -P0, m1h);
+  acc_limbs(Hi, Lo, P1, m0h);
+  k2 = exdiv_limbs(Hi, Lo, dv); // -H2, columns s0, s1, h
+  d = flip ? -D : D;
 }
 
-// Exact decision of one candidate that no point lies strictly below, with
-// lanes as points: a lower facet when exactly its k + 1 vertices vanish, a
-// tie otherwise.
+// Exact decision of one candidate (its record word, wave-uniform) that the
+// filter could not reject, with lanes as points: its cofactors derived
+// again, u_j = k0 s0 + k1 s1 + k2 s2 + d h summed in limbs as
+// u = 2^29 hi + (lo mod 2^29) (every product a 32 x 32 -> 64 multiply-add;
+// the low limbs sum below 2^61, the high limbs below 2^62).  Rejected when
+// a point lies strictly below; a lower facet when exactly its k + 1
+// vertices vanish; a tie otherwise.
 template <class CX>
-__device__ __forceinline__ void decide_exact(CX &cx, const int32_t *rc, int t) {
+__device__ __forceinline__ void decide_exact(CX &cx, int32_t meta) {
   const int lane = lane_id();
+  const int t = (meta >> REC_TABLE_BIT) & 3;
+  const int c1 = meta & 255, c2 = (meta >> 8) & 255, c3 = (meta >> 16) & 255;
+  const TableInfo ti = cx.lds->info[t];
+  Div dv;
+  dv.e = ti.e;
+  dv.inv = ti.inv;
+  int64_t k0, k1, k2;
+  int32_t D, d;
+  triple_cofactors(cx.lds, t, c1, c2, c3, dv, ti.prevneg != 0, k0, k1, k2, D, d);
   const int4 row = cx.lds->rowS[t][lane];
   const int2 hx = cx.lds->rowH[t][lane];
-  const UVal u = u_exact(rc, row.x, row.y, row.z, hx.x, hx.y);
-  const bool on = u.hi == 0 && (u.lo & DENSE_LMASK) == 0;
+  const int64_t lo = (int64_t)row.x * (int32_t)(k0 & DENSE_LMASK) + (int64_t)row.y * (int32_t)(k1 & DENSE_LMASK) +
+                     (int64_t)row.z * (int32_t)(k2 & DENSE_LMASK) + (int64_t)hx.y * d;
+  const int64_t hi = (lo >> DENSE_LIMB) + (int64_t)row.x * (int32_t)(k0 >> DENSE_LIMB) +
+                     (int64_t)row.y * (int32_t)(k1 >> DENSE_LIMB) + (int64_t)row.z * (int32_t)(k2 >> DENSE_LIMB) +
+                     (int64_t)hx.x * d;
+  const bool on = hi == 0 && (lo & DENSE_LMASK) == 0;
   const uint64_t zero = ballot(on && lane < cx.N);
-  const uint64_t below = ballot(u.hi < 0 && lane < cx.N);
+  const uint64_t below = ballot(hi < 0 && lane < cx.N);
   if (below) return; // a point below within the filter's band
-  const int vtx = rc[7];
-  const int c1 = vtx & 255, c2 = (vtx >> 8) & 255, c3 = (vtx >> 16) & 255;
-  const uint64_t verts = cx.lds->info[t].chosen | (1ull << c1) | (1ull << c2) | (1ull << c3);
+  const uint64_t verts = ti.chosen | (1ull << c1) | (1ull << c2) | (1ull << c3);
   if (zero != verts) {
     if (lane == 0) cx.lds->tally.tie = 1;
     return;
   }
-  const int32_t d = rc[6];
   if (lane == 0) {
     cx.lds->tally.acc += (unsigned long long)(d < 0 ? -(int64_t)d : (int64_t)d);
     cx.lds->tally.cells += 1;
@@ -284,12 +320,8 @@ __device__ __forceinline__ void test_batch(CX &cx, int n, int logC) {
   const int p = lane >> logC, q = lane & ((1 << logC) - 1);
   const bool valid = p < n;
   const int slot = (cx.head + (valid ? p : 0)) & (DENSE_RING - 1);
-  int32_t rc[8];
-  {
-    const int4 a = *(const int4 *)&cx.lds->rec[slot][0];
-    const int4 b = *(const int4 *)&cx.lds->rec[slot][4];
-    rc[0] = a.x, rc[1] = a.y, rc[2] = a.z, rc[3] = a.w, rc[4] = b.x, rc[5] = b.y, rc[6] = b.z, rc[7] = b.w;
-  }
+  const int4 rx = cx.lds->recX[slot];
+  const int32_t meta = cx.lds->recM[slot];
   // Filter test, exact in its rejections.  A record's shift sg makes its
   // coefficients k_a >> sg fit 31 bits and its node's heights h >> sg fit 32
   // (the row table holds h >> sn, sn <= sg; a lane shifts on by sg - sn).
@@ -302,12 +334,11 @@ __device__ __forceinline__ void test_batch(CX &cx, int n, int logC) {
   // candidate with a point proved below is rejected; one without is decided
   // exactly below.
   const int iters = (cx.N + (1 << logC) - 1) >> logC; // rows past N are zero rows
-  const int t = rec_table(rc);
-  const int sg = rec_shift(rc);
+  const int t = (meta >> REC_TABLE_BIT) & 3;
+  const int sg = (int)((uint32_t)meta >> REC_SHIFT_BIT);
   const uint2 sb = *(const uint2 *)&cx.lds->info[t].sig; // (sig, band) of the record's table
   const int dl = sg - (int)sb.x;
-  const int32_t x0 = limb_shift(rc[0], rc[1], sg), x1 = limb_shift(rc[2], rc[3], sg), x2 = limb_shift(rc[4], rc[5], sg);
-  const int32_t d = rc[6];
+  const int32_t x0 = rx.x, x1 = rx.y, x2 = rx.z, d = rx.w;
   const int64_t bnd = sg > 0 ? (int64_t)sb.y + (d < 0 ? -(int64_t)d : (int64_t)d) - 1 : 0;
   const int4 *rowS = cx.lds->rowS[t];
   int32_t neg = 0, first = 0;
@@ -350,10 +381,7 @@ __device__ __forceinline__ void test_batch(CX &cx, int n, int logC) {
   while (sm) { // rare: no point proved below (a cell, a tie, or a point within the band)
     const int l = __builtin_ctzll(sm);
     sm &= sm - 1;
-    int32_t b[8];
-#pragma unroll
-    for (int i = 0; i < 8; i++) b[i] = rl32(rc[i], l);
-    decide_exact(cx, b, rec_table(b));
+    decide_exact(cx, rl32(meta, l));
   }
 #pragma unroll
   for (int i = 0; i < DENSE_TABLES; i++)
@@ -406,49 +434,14 @@ __device__ __forceinline__ void setup_pass(CX &cx) {
   const bool prevneg = ti.prevneg != 0;
   int c1, c2, c3;
   unrank3(act ? r : 0, &c1, &c2, &c3); // (an inactive lane reads rows 2, 1, 0, in range)
-  const int4 *RS = cx.lds->rowS[t];
-  const int2 *RH = cx.lds->rowH[t];
-  const int4 a1 = RS[c1], a2 = RS[c2], a3 = RS[c3];
-  const int2 x1 = RH[c1], x2 = RH[c2], x3 = RH[c3];
-  // heights split at bit 29: h = hh 2^29 + l, 0 <= l < 2^29
-  const int32_t hh1 = x1.x, l1 = x1.y, hh2 = x2.x, l2 = x2.y, hh3 = x3.x, l3 = x3.y;
-  const int32_t s01 = a1.x, s11 = a1.y, s21 = a1.z;
-  const int32_t s02 = a2.x, s12 = a2.y, s22 = a2.z;
-  const int32_t s03 = a3.x, s13 = a3.y, s23 = a3.z;
-  // 2 x 2 minors of rows c1, c2 (T+2 minors), spatial and with the height column
-  const int32_t m01 = exdiv32((int64_t)s01 * s12 - (int64_t)s11 * s02, dv);
-  const int32_t m02 = exdiv32((int64_t)s01 * s22 - (int64_t)s21 * s02, dv);
-  const int32_t m12 = exdiv32((int64_t)s11 * s22 - (int64_t)s21 * s12, dv);
-  const int64_t m0h = exdiv_limbs((int64_t)s01 * hh2 - (int64_t)hh1 * s02, (int64_t)s01 * l2 - (int64_t)l1 * s02, dv);
-  const int64_t m1h = exdiv_limbs((int64_t)s11 * hh2 - (int64_t)hh1 * s12, (int64_t)s11 * l2 - (int64_t)l1 * s12, dv);
-  const int64_t m2h = exdiv_limbs((int64_t)s21 * hh2 - (int64_t)hh1 * s22, (int64_t)s21 * l2 - (int64_t)l1 * s22, dv);
-  // 3 x 3 minors of rows c1, c2, c3 (T+3 minors) by expansion along row c3:
-  // the spatial one D first, then, with row c3 multiplied by the
-  // orientation sign(D) sign(prev) (every minor below is linear in it), the
-  // coefficients of u_j: k0 = -H0, k1 = H1, k2 = -H2 (H_a: column a deleted)
-  const int32_t D = exdiv32((int64_t)s03 * m12 - (int64_t)s13 * m02 + (int64_t)s23 * m01, dv);
+  int64_t k0, k1, k2;
+  int32_t D, d;
+  triple_cofactors(cx.lds, t, c1, c2, c3, dv, prevneg, k0, k1, k2, D, d);
   const bool nz = act && D != 0;
   if constexpr (S) {
     cx.setups++;
     cx.triples += base;
   }
-  const bool flip = (D < 0) != prevneg;
-  const int32_t P0 = flip ? -s03 : s03, P1 = flip ? -s13 : s13, P2 = flip ? -s23 : s23;
-  const int32_t Ph = flip ? -hh3 : hh3, Pl = flip ? -l3 : l3;
-  int64_t Hi, Lo;
-  Hi = (int64_t)(-Ph) * m12, Lo = (int64_t)(-Pl) * m12;
-  acc_limbs(Hi, Lo, -P1, m2h);
-  acc_limbs(Hi, Lo, P2, m1h);
-  const int64_t k0 = exdiv_limbs(Hi, Lo, dv); // -H0, columns s1, s2, h
-  Hi = (int64_t)Ph * m02, Lo = (int64_t)Pl * m02;
-  acc_limbs(Hi, Lo, P0, m2h);
-  acc_limbs(Hi, Lo, -P2, m0h);
-  const int64_t k1 = exdiv_limbs(Hi, Lo, dv); // H1, columns s0, s2, h
-  Hi = (int64_t)(-Ph) * m01, Lo = (int64_t)(-Pl) * m01;
-  acc_limbs(Hi, Lo, -P0, m1h);
-  acc_limbs(Hi, Lo, P1, m0h);
-  const int64_t k2 = exdiv_limbs(Hi, Lo, dv); // -H2, columns s0, s1, h
-  const int32_t d = flip ? -D : D;
   const uint64_t m = ballot(nz);
   // the filter's shift: k_a >> sg within [-2^30, 2^30), and at least the table's
   const uint64_t mk = (uint64_t)(k0 ^ (k0 >> 63)) | (uint64_t)(k1 ^ (k1 >> 63)) | (uint64_t)(k2 ^ (k2 >> 63));
@@ -468,13 +461,8 @@ __device__ __forceinline__ void setup_pass(CX &cx) {
   if (nz) {
     const uint32_t below = (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1));
     const int slot = (cx.head + cx.nrec + (int)below) & (DENSE_RING - 1);
-    int4 x, y;
-    x.x = (int32_t)(k0 & DENSE_LMASK), x.y = (int32_t)(k0 >> DENSE_LIMB);
-    x.z = (int32_t)(k1 & DENSE_LMASK), x.w = (int32_t)(k1 >> DENSE_LIMB);
-    y.x = (int32_t)(k2 & DENSE_LMASK), y.y = (int32_t)(k2 >> DENSE_LIMB);
-    y.z = d, y.w = c1 | (c2 << 8) | (c3 << 16) | (t << REC_TABLE_BIT) | (sg << REC_SHIFT_BIT);
-    *(int4 *)&cx.lds->rec[slot][0] = x;
-    *(int4 *)&cx.lds->rec[slot][4] = y;
+    cx.lds->recX[slot] = make_int4((int32_t)(k0 >> sg), (int32_t)(k1 >> sg), (int32_t)(k2 >> sg), d);
+    cx.lds->recM[slot] = c1 | (c2 << 8) | (c3 << 16) | (t << REC_TABLE_BIT) | (sg << REC_SHIFT_BIT);
   }
   const int added = __builtin_popcountll(m);
   if constexpr (S) cx.leaves += (uint32_t)added;
