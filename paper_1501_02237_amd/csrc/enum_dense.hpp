@@ -91,6 +91,9 @@ struct alignas(16) DenseLds {
   int4 qS[64];  // s0, s1, s2, s3
   int32_t qh[64]; // h >> its shift
   int2 qx[8];   // h split at bit 29 (hh, hl) of the points below DENSE_TAIL
+  // rows of the tail's children (child c0, point x < c0 at C(c0,2) - 3 + x)
+  int4 ctS[18];
+  int2 ctH[18];
   Tally tally;
 };
 // four blocks of four waves fit a compute unit's 160 KiB
@@ -205,19 +208,17 @@ __device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
 
 
 
-// Cofactors of the triple {c1 > c2 > c3} of the node in row table t, from
-// its rows (heights split at bit 29: h = hh 2^29 + l, 0 <= l < 2^29) and its
+// Cofactors of the triple {c1 > c2 > c3} of a node, from its rows (RS:
+// s0, s1, s2; RH: heights split at bit 29: h = hh 2^29 + l, 0 <= l < 2^29) and its
 // pivot data: the 2 x 2 minors of rows c1, c2 (T+2 minors), spatial and
 // with the height column; then the 3 x 3 minors of rows c1, c2, c3 (T+3
 // minors) by expansion along row c3: the spatial one D first, then, with
 // row c3 multiplied by the orientation sign(D) sign(prev) (every minor
 // below is linear in it), the coefficients of u_j: k0 = -H0, k1 = H1,
 // k2 = -H2 (H_a: column a deleted); d is D times the same sign.
-__device__ __forceinline__ void triple_cofactors(const DenseLds *L, int t, int c1, int c2, int c3, const Div &dv,
+__device__ __forceinline__ void triple_cofactors(const int4 *RS, const int2 *RH, int c1, int c2, int c3, const Div &dv,
                                                  bool prevneg, int64_t &k0, int64_t &k1, int64_t &k2, int32_t &D,
                                                  int32_t &d) {
-  const int4 *RS = L->rowS[t];
-  const int2 *RH = L->rowH[t];
   const int4 a1 = RS[c1], a2 = RS[c2], a3 = RS[c3];
   const int2 x1 = RH[c1], x2 = RH[c2], x3 = RH[c3];
   const int32_t hh1 = x1.x, l1 = x1.y, hh2 = x2.x, l2 = x2.y, hh3 = x3.x, l3 = x3.y;
@@ -268,7 +269,7 @@ __device__ __forceinline__ void decide_exact(CX &cx, int32_t meta) {
   dv.inv = ti.inv;
   int64_t k0, k1, k2;
   int32_t D, d;
-  triple_cofactors(cx.lds, t, c1, c2, c3, dv, ti.prevneg != 0, k0, k1, k2, D, d);
+  triple_cofactors(cx.lds->rowS[t], cx.lds->rowH[t], c1, c2, c3, dv, ti.prevneg != 0, k0, k1, k2, D, d);
   const int4 row = cx.lds->rowS[t][lane];
   const int2 hx = cx.lds->rowH[t][lane];
   const int64_t lo = (int64_t)row.x * (int32_t)(k0 & DENSE_LMASK) + (int64_t)row.y * (int32_t)(k1 & DENSE_LMASK) +
@@ -436,7 +437,7 @@ __device__ __forceinline__ void setup_pass(CX &cx) {
   unrank3(act ? r : 0, &c1, &c2, &c3); // (an inactive lane reads rows 2, 1, 0, in range)
   int64_t k0, k1, k2;
   int32_t D, d;
-  triple_cofactors(cx.lds, t, c1, c2, c3, dv, prevneg, k0, k1, k2, D, d);
+  triple_cofactors(cx.lds->rowS[t], cx.lds->rowH[t], c1, c2, c3, dv, prevneg, k0, k1, k2, D, d);
   const bool nz = act && D != 0;
   if constexpr (S) {
     cx.setups++;
@@ -682,6 +683,30 @@ __device__ __forceinline__ void quad_cofactors(const DenseLds *L, int c0, int c1
   d = flip ? -D : D;
 }
 
+// The pivot of a tail child (its row r in the node's table): the first
+// nonzero spatial column p (piv = 0 when there is none: a degenerate
+// child), and the other three columns with their entries.
+struct ChildPivot {
+  int p;
+  int32_t piv;
+  int col[3];
+  int32_t r[3];
+};
+__device__ __forceinline__ int32_t pick4(const int4 &v, int i) {
+  return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+__device__ __forceinline__ ChildPivot child_pivot(const int4 R) {
+  ChildPivot cp;
+  cp.p = R.x != 0 ? 0 : R.y != 0 ? 1 : R.z != 0 ? 2 : 3;
+  cp.piv = pick4(R, cp.p);
+  cp.col[0] = cp.p == 0 ? 1 : 0;
+  cp.col[1] = cp.p <= 1 ? 2 : 1;
+  cp.col[2] = cp.p <= 2 ? 3 : 2;
+#pragma unroll
+  for (int i = 0; i < 3; i++) cp.r[i] = pick4(R, cp.col[i]);
+  return cp;
+}
+
 // C(c, 4) for 3 <= c <= 7
 __device__ __forceinline__ uint32_t c4_small(int c) { return c <= 3 ? 0u : c == 4 ? 1u : c == 5 ? 5u : c == 6 ? 15u : 35u; }
 
@@ -731,16 +756,66 @@ __device__ __forceinline__ void quad_tail(CX &cx, const St<4> &st, int lo_c, int
   const uint32_t band = wave_umax((uint32_t)abs(st.s[0]) + (uint32_t)abs(st.s[1]) + (uint32_t)abs(st.s[2]) +
                                   (uint32_t)abs(st.s[3]));
   wave_sync_lds();
-  // 3. lanes 2^logC p .. 2^logC p + 2^logC - 1 set up quadruple p (the same
-  //    values in each; an inactive lane takes rank 0 = {3, 2, 1, 0})
+  const Div dv = make_div(st.prev);
+  // 3. the children's rows, one Bareiss step each (lane C(c0,2) - 3 + x:
+  //    child c0 < DENSE_TAIL, point x < c0), for the triple cofactors below
+  {
+    const int cc = 3 + (lane >= 3) + (lane >= 7) + (lane >= 12);
+    const int x = lane - (int)(c2_of(cc) - 3u);
+    if (lane < 18 && cc <= hi_c) {
+      const ChildPivot cp = child_pivot(cx.lds->qS[cc]);
+      const int4 Rx = cx.lds->qS[x];
+      const int2 X0 = cx.lds->qx[cc], Xx = cx.lds->qx[x];
+      const int32_t rxp = pick4(Rx, cp.p);
+      int4 o;
+      o.x = exdiv32((int64_t)cp.piv * pick4(Rx, cp.col[0]) - (int64_t)cp.r[0] * rxp, dv);
+      o.y = exdiv32((int64_t)cp.piv * pick4(Rx, cp.col[1]) - (int64_t)cp.r[1] * rxp, dv);
+      o.z = exdiv32((int64_t)cp.piv * pick4(Rx, cp.col[2]) - (int64_t)cp.r[2] * rxp, dv);
+      o.w = 0;
+      const int64_t hc = exdiv_limbs((int64_t)cp.piv * Xx.x - (int64_t)X0.x * rxp,
+                                     (int64_t)cp.piv * Xx.y - (int64_t)X0.y * rxp, dv);
+      cx.lds->ctS[lane] = o;
+      cx.lds->ctH[lane] = make_int2((int32_t)(hc >> DENSE_LIMB), (int32_t)(hc & DENSE_LMASK));
+    }
+    wave_sync_lds();
+  }
+  // 4. lanes 2^logC p .. 2^logC p + 2^logC - 1 set up quadruple p (the same
+  //    values in each; an inactive lane takes rank 0 = {3, 2, 1, 0}): the
+  //    triple {c1, c2, c3} of child c0 (its pivot piv), whose coefficients
+  //    k'_i over the child's columns turn into this node's: the same k'_i
+  //    on the columns other than the child's pivot column p, and
+  //    kap_p = -(sum_i k'_i R_c0[col_i] + d h_c0) / piv there (the child's
+  //    residual of point j is (piv R_j - R_j[p] R_c0) / prev, so
+  //    prev u'_j = piv u_j - R_j[p] (sum_i k'_i R_c0[col_i] + d h_c0), with
+  //    u_j over this node's rows); the orientation then moves from
+  //    sign(piv) to sign(prev).
   const uint32_t r = act ? q_lo + (uint32_t)p : 0u;
   const int c0 = 3 + (r >= 1) + (r >= 5) + (r >= 15);
   int c1, c2, c3;
   unrank3(r - c4_small(c0), &c1, &c2, &c3);
-  const Div dv = make_div(st.prev);
   int64_t kap[4];
   int32_t D, d;
-  quad_cofactors(cx.lds, c0, c1, c2, c3, dv, st.prev < 0, kap, D, d);
+  {
+    const ChildPivot cp = child_pivot(cx.lds->qS[c0]);
+    const Div dvc = make_div(cp.piv != 0 ? cp.piv : 1);
+    const int b0 = (int)c2_of(c0) - 3;
+    int64_t k[3];
+    triple_cofactors(cx.lds->ctS, cx.lds->ctH, b0 + c1, b0 + c2, b0 + c3, dvc, cp.piv < 0, k[0], k[1], k[2], D, d);
+    if (cp.piv == 0) D = 0; // the child is degenerate: every candidate below it has D = 0
+    const int2 X0 = cx.lds->qx[c0];
+    int64_t Hi = (int64_t)X0.x * d, Lo = (int64_t)X0.y * d;
+    acc_limbs(Hi, Lo, cp.r[0], k[0]);
+    acc_limbs(Hi, Lo, cp.r[1], k[1]);
+    acc_limbs(Hi, Lo, cp.r[2], k[2]);
+    const int64_t kp = -exdiv_limbs(Hi, Lo, dvc);
+    const bool turn = (st.prev < 0) != (cp.piv < 0);
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      const int64_t v = c < cp.p ? (c < 3 ? k[c] : 0) : c == cp.p ? kp : k[c > 0 ? c - 1 : 0];
+      kap[c] = turn ? -v : v;
+    }
+    d = turn ? -d : d;
+  }
   const bool nz = act && D != 0;
   // 4. filter test (as in test_batch), 2^logC lanes per quadruple
   const uint64_t mk = (uint64_t)(kap[0] ^ (kap[0] >> 63)) | (uint64_t)(kap[1] ^ (kap[1] >> 63)) |
