@@ -48,9 +48,9 @@ TRAFFIC = {
     "sources": ("enum_device.hpp", "enum_dense.hpp", "exact_div.hpp", "kernels_k10.hip", "runtime.cpp",
                 "bdeg_internal.hpp", "lifting.hpp"),
     "table": os.path.join("tuning", "gfx950.json"),
-    "sha256": "0353d0a17f1b03116abbd0d70099ccc6d8340f87f73f4f6d14c5f01da614cce9",
-    "fetch_kib": 27088.3, "fetch_scale": 262144.0 / 131088.6,
-    "write_kib": 18323.0, "write_scale": 262144.0 / 262144.0,
+    "sha256": "79368f51088b87163eed565ec62e5cfb696d0ea7a38a4a69fdea4a21720d432d",
+    "fetch_kib": 32422.8, "fetch_scale": 262144.0 / 131087.75,
+    "write_kib": 829563.6, "write_scale": 262144.0 / 262144.0,
 }
 
 
