@@ -193,6 +193,7 @@ void points_job(Job &job, const int32_t *points, const int64_t *heights, int N, 
   job.kmin = job.kmax = k;
   const uint64_t total = binom_u64(N, k + 1);
   const uint64_t hi = std::min(rank_hi, total), lo = std::min(rank_lo, hi);
+  if (lo == 0 && hi == total && total > 0) job.sys[0].flags |= SYS_SORTED; // every candidate: may relabel
   std::vector<TileC> tc;
   tiles_range(N, k, 0, lo, hi, max_cost ? max_cost : choose_max_cost(hi - lo, default_waves(k, k, 4)), tc);
   job_order_units(job, tc);

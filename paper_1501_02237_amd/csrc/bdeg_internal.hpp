@@ -26,7 +26,7 @@ struct SysDesc {
   uint64_t lift_key; // counter-based lifting key for the current attempt
   uint64_t seed;      // the system's lifting stream is (seed, sys_index, attempt)
   uint32_t sys_index; // stream index: 0 for every seeded system (one-shot, batch and served alike)
-  uint32_t flags;     // SYS_DENSE
+  uint32_t flags;     // SYS_DENSE, SYS_SORTED
 };
 
 // A work unit: the candidates whose top elements (colex) are exactly the set
@@ -89,6 +89,9 @@ bool device_bounds_ok(const int32_t *pts, int N, int k, uint64_t height_span, in
 // lanes-as-points schedule everywhere (bdeg_set_schedule).
 bool dense_ok(const int32_t *pts, int N, int k, uint64_t height_span);
 constexpr uint32_t SYS_DENSE = 1; // SysDesc.flags: units run in the lane-dense kernel
+// SysDesc.flags: the units cover every candidate of the system, so the
+// lane-dense kernel may relabel its points (it orders them by lifted height)
+constexpr uint32_t SYS_SORTED = 2;
 
 // ------------------------------------------------------------ tiling
 uint64_t binom_u64(int n, int r); // saturates at UINT64_MAX

@@ -87,6 +87,7 @@ struct alignas(16) DenseLds {
   int4 recX[DENSE_RING];    // a candidate's filter coefficients k0 >> sg, k1 >> sg, k2 >> sg and d
   int32_t recM[DENSE_RING]; // c1 | c2 << 8 | c3 << 16 | table | shift sg
   TableInfo info[DENSE_TABLES];
+  uint8_t perm[64]; // lane j holds point perm[j] of the system (its lifted-height order, or j)
   // rows of the node whose tail quadruples are set up (four spatial columns)
   int4 qS[64];  // s0, s1, s2, s3
   int32_t qh[64]; // h >> its shift
@@ -208,6 +209,41 @@ __device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
 
 
 
+// A vertex set in the system's own point labels (lane j holds point perm[j]).
+template <class CX>
+__device__ __forceinline__ uint64_t unlabel(const CX &cx, uint64_t verts) {
+  uint64_t m = 0;
+  while (verts) {
+    const int b = __builtin_ctzll(verts);
+    verts &= verts - 1;
+    m |= 1ull << cx.lds->perm[b];
+  }
+  return m;
+}
+
+// The lane order of a system's points: when its units cover all its
+// candidates (SYS_SORTED) the kernel relabels the points in ascending lifted
+// height (ties by index), which changes no candidate's decision but lets a
+// test batch, which walks the points in label order, meet a point below each
+// candidate sooner; otherwise the identity.  Called by every lane.
+template <class CX>
+__device__ __forceinline__ void dense_order(CX &cx, const SysDesc &sd, const int64_t *__restrict__ hts) {
+  const int lane = lane_id();
+  int rank = lane;
+  if (sd.flags & SYS_SORTED) {
+    const int64_t h = lane < sd.N ? hts[sd.ht_off + lane] : INT64_MAX;
+    rank = 0;
+    for (int i = 0; i < 64; i++) {
+      const int64_t hi = (int64_t)(((uint64_t)(uint32_t)rl32((int32_t)((uint64_t)h >> 32), i) << 32) |
+                                   (uint32_t)rl32((int32_t)(uint32_t)(uint64_t)h, i));
+      rank += (hi < h || (hi == h && i < lane)) ? 1 : 0;
+    }
+  }
+  wave_sync_lds();
+  cx.lds->perm[rank] = (uint8_t)lane;
+  wave_sync_lds();
+}
+
 // Cofactors of the triple {c1 > c2 > c3} of a node, from its rows (RS:
 // s0, s1, s2; RH: heights split at bit 29: h = hh 2^29 + l, 0 <= l < 2^29) and its
 // pivot data: the 2 x 2 minors of rows c1, c2 (T+2 minors), spatial and
@@ -290,7 +326,7 @@ __device__ __forceinline__ void decide_exact(CX &cx, int32_t meta) {
     cx.lds->tally.acc += (unsigned long long)(d < 0 ? -(int64_t)d : (int64_t)d);
     cx.lds->tally.cells += 1;
   }
-  if constexpr (CX::emit) emit_cell(cx, verts);
+  if constexpr (CX::emit) emit_cell(cx, unlabel(cx, verts));
 }
 
 // The points of a full test batch (one candidate per lane) until every
@@ -914,7 +950,7 @@ __device__ __forceinline__ void quad_tail(CX &cx, const St<4> &st, int lo_c, int
         cx.lds->tally.acc += (unsigned long long)(dl_ < 0 ? -(int64_t)dl_ : (int64_t)dl_);
         cx.lds->tally.cells += 1;
       }
-      if constexpr (CX::emit) emit_cell(cx, verts);
+      if constexpr (CX::emit) emit_cell(cx, unlabel(cx, verts));
     }
   }
 }
@@ -1016,9 +1052,10 @@ __device__ __forceinline__ void dense_tile(CX &cx, const SysDesc &sd, const int3
 #pragma unroll
   for (int i = 0; i < K; i++) P[i] = 0;
   if (valid) {
+    const int src = cx.lds->perm[cx.j];
 #pragma unroll
-    for (int i = 0; i < K; i++) P[i] = pts[sd.pt_off + cx.j * K + i];
-    w = hts[sd.ht_off + cx.j];
+    for (int i = 0; i < K; i++) P[i] = pts[sd.pt_off + src * K + i];
+    w = hts[sd.ht_off + src];
   }
   const int base = 63 - __builtin_clzll(cx.mask);
   const int64_t wb = (int64_t)(((uint64_t)(uint32_t)rl32((int32_t)(uint32_t)((uint64_t)w >> 32), base) << 32) |
@@ -1175,6 +1212,7 @@ dense_kernel(const SysDesc *__restrict__ sys, const int32_t *__restrict__ pts, c
       sd = sys[tl.sys];
       cx.N = sd.N;
       cx.k = sd.k;
+      dense_order(cx, sd, hts);
     }
     dense_unit<KLO, KHI>(cx, tl, sd, pts, hts);
     dense_commit(cx, sd, &acc[cur_sys], cnt, true);

@@ -108,7 +108,7 @@ void job_build_seeded(Job &job, const std::vector<HostSys> &systems, uint64_t ma
     d.lift_key = lift_key(h.seed, 0u, h.attempt);
     d.seed = h.seed;
     d.sys_index = 0;
-    d.flags = dense ? SYS_DENSE : 0;
+    d.flags = dense ? SYS_DENSE | SYS_SORTED : 0; // every unit of the system
     job.sys.push_back(d);
     job.pts.insert(job.pts.end(), h.pts.begin(), h.pts.end());
     ht += h.N;

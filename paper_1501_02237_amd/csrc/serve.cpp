@@ -209,7 +209,7 @@ void bdeg_server::start_attempt(Request *r) {
   d.seed = r->hs.seed;
   d.sys_index = 0;
   r->dense = dense_ok(r->hs.pts.data(), d.N, d.k, (1ull << d.lift_bits) - 1);
-  d.flags = r->dense ? SYS_DENSE : 0;
+  d.flags = r->dense ? SYS_DENSE | SYS_SORTED : 0; // served whole
   (void)hipMemcpyAsync(d_sys + r->slot, &d, sizeof(SysDesc), hipMemcpyHostToDevice, stream);
   // units are taken round-robin across requests in small steps, so their
   // order within a request does not matter: no sort
