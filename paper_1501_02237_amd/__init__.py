@@ -27,6 +27,8 @@ BDEG_E_DEVICE = -5
 BDEG_E_NOMEM = -6
 BDEG_E_STATE = -7
 BDEG_F_NEEDS_CONSISTENCY = 1
+BDEG_F_PRUNED = 2
+PRUNE_MIN_CANDIDATES = 1 << 27
 MAX_N = 63
 MAX_K = 18
 MAX_ATTEMPTS = 16

@@ -91,13 +91,72 @@ int prepare_many(const int64_t *A_concat, const int32_t *m, const int32_t *n, in
   return BDEG_OK;
 }
 
+// Host plan of the prefix-pruned enumeration (prefixes, unit runs, buckets).
+struct PrunePlan {
+  int W = 0, d = 0;
+  std::vector<uint64_t> items;
+  std::vector<uint16_t> chunk_start;
+  std::vector<uint8_t> run_lo, run_hi;
+  uint32_t off[64] = {0};
+  uint64_t cap_units = 0;
+};
+
+static int prune_plan(int N, int k, int width, PrunePlan &P);
+static int prune_run(Device *D, const PrunePlan &P, const int32_t *points, const int64_t *heights, int N, int k,
+                     bdeg_u128 *nvol, int32_t *tie, uint64_t *cells, bdeg_prune_stats *ps);
+
+// The cost model's choice for a one-shot system: the prefix-pruned
+// enumeration on the seeded heights of each attempt (drawn on the host by
+// the device's own stream), ties redrawn as in the plain path.  Returns
+// false, leaving the system to the plain path, when the model or the
+// pruned path's limits say no; a device error is reported in *rc.
+static bool solve_pruned(Device *D, HostSys &h, bdeg_result &r, int *rc) {
+  *rc = BDEG_OK;
+  if (schedule_mode() != BDEG_SCHED_AUTO || binom_u64(h.N, h.k + 1) < BDEG_PRUNE_MIN_CANDIDATES) return false;
+  PrunePlan P;
+  if (prune_plan(h.N, h.k, 0, P) != BDEG_OK) return false;
+  std::vector<int64_t> hts((size_t)h.N);
+  for (;;) {
+    const uint64_t key = lift_key(h.seed, 0, h.attempt);
+    for (int j = 0; j < h.N; j++) hts[(size_t)j] = lift_height(key, j, h.lift_bits);
+    if (h.attempt == 0 && check_points(h.pts.data(), hts.data(), h.N, h.k) != BDEG_OK) return false;
+    bdeg_u128 nv{0, 0};
+    int32_t tie = 0;
+    uint64_t cells = 0;
+    if ((*rc = prune_run(D, P, h.pts.data(), hts.data(), h.N, h.k, &nv, &tie, &cells, nullptr))) return true;
+    r.attempts = (int32_t)h.attempt + 1;
+    r.flags |= BDEG_F_PRUNED;
+    if (!tie) {
+      r.nvol = nv;
+      r.cells = cells;
+      r.status = BDEG_OK;
+      return true;
+    }
+    if (h.attempt + 1 >= (uint32_t)BDEG_MAX_ATTEMPTS) {
+      r.status = BDEG_E_TIE;
+      return true;
+    }
+    h.attempt++;
+  }
+}
+
 // Run device systems to completion: tie retries redraw the lifting of the
 // tied systems only.  `first` (optional) is an already-launched job holding
-// all of `dev` in order.
+// all of `dev` in order; without it, systems the cost model picks run the
+// prefix-pruned enumeration instead (solve_pruned).
 int finish_device(Device *D, std::vector<HostSys> &dev, std::vector<bdeg_result> &res, Job *first,
                   DevCounters *cnt_out, int32_t *redraws_out) {
-  std::vector<int> pending(dev.size());
-  for (size_t i = 0; i < dev.size(); i++) pending[i] = (int)i;
+  std::vector<int> pending;
+  for (size_t i = 0; i < dev.size(); i++) {
+    if (!first) {
+      int rc = BDEG_OK;
+      if (solve_pruned(D, dev[i], res[dev[i].input_index], &rc)) {
+        if (rc) return rc;
+        continue;
+      }
+    }
+    pending.push_back((int)i);
+  }
   Job local;
   for (int round = 0; !pending.empty(); round++) {
     Job *job = (round == 0 && first) ? first : &local;
@@ -719,22 +778,21 @@ int bdeg_nvol_points(const int32_t *points, const int64_t *heights, int32_t N, i
   return BDEG_OK;
 }
 
-int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, int32_t width,
-                            bdeg_u128 *nvol, int32_t *tie, uint64_t *cells, bdeg_prune_stats *ps) {
-  if (!nvol || !tie) return BDEG_E_ARG;
-  int rc = check_points(points, heights, N, k);
-  if (rc) return rc;
+namespace bdeg {
+
+static int prune_plan(int N, int k, int width, PrunePlan &P) {
   // prefix states with W free columns: W = width, or 5 widened while there
   // are more than 2^18 prefixes (the tests then cost more than they save)
-  int W = width > 0 ? width : std::min(k, 5);
+  int &W = P.W;
+  W = width > 0 ? width : std::min(k, 5);
   if (W < 1 || W > PRUNE_WMAX || W > k) return BDEG_E_ARG;
   if (width <= 0)
     while (W < PRUNE_WMAX && W < k && binom_u64(N - W, k + 1 - W) > (1ull << 18)) W++;
-  const int d = k + 1 - W; // prefix size; its lowest element is >= W
+  const int d = P.d = k + 1 - W; // prefix size; its lowest element is >= W
   const uint64_t n_items = binom_u64(N - W, d);
   if (n_items > BDEG_PRUNE_MAX_PREFIXES) return BDEG_E_TOO_LARGE;
   // the prefixes: d-subsets of {W, .., N-1}; each kept one gives e - W + 1 units
-  std::vector<uint64_t> items;
+  std::vector<uint64_t> &items = P.items;
   items.reserve((size_t)n_items);
   // d-subsets of {0, .., N-W-1} in increasing order (Gosper), shifted up by W;
   // a prefix with lowest point e gives one unit for each next element
@@ -751,8 +809,9 @@ int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32
   // (each run at most the plain plan's unit cost); one run [c, c] when F + c
   // is already a whole candidate (W = 1)
   const uint64_t max_cost = choose_max_cost(binom_u64(N, k + 1), default_waves(k, k, 4));
-  std::vector<uint16_t> chunk_start(65, 0);
-  std::vector<uint8_t> run_lo, run_hi;
+  std::vector<uint16_t> &chunk_start = P.chunk_start;
+  chunk_start.assign(65, 0);
+  std::vector<uint8_t> &run_lo = P.run_lo, &run_hi = P.run_hi;
   for (int c = 0; c < 64; c++) {
     chunk_start[c] = (uint16_t)run_lo.size();
     if (c < W - 1 || c >= N) continue;
@@ -775,18 +834,27 @@ int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32
   chunk_start[64] = (uint16_t)run_lo.size();
   if (run_lo.empty()) return BDEG_E_TOO_LARGE;
   // bucket c holds chunk c of every prefix with e > c; laid out from c = N-1 down
-  uint32_t off[64] = {0};
-  uint64_t cap_units = 0, above = 0;
+  uint32_t *off = P.off;
+  uint64_t &cap_units = P.cap_units, above = 0;
   for (int c = N - 1; c >= W - 1; c--) {
     off[c] = (uint32_t)std::min<uint64_t>(cap_units, 0xFFFFFFFFull);
     cap_units += above * (uint64_t)(chunk_start[c + 1] - chunk_start[c]); // prefixes whose lowest point is above c
     above += per_c[c];
   }
   if (cap_units == 0 || cap_units > 0xFFFFFFFFull) return BDEG_E_TOO_LARGE;
-  int st;
-  Device *D = device_get(&st);
-  if (!D) return st;
-  std::lock_guard<std::mutex> lk(D->mu);
+  return BDEG_OK;
+}
+
+// Device part of the prefix-pruned enumeration (the device lock held).
+static int prune_run(Device *D, const PrunePlan &P, const int32_t *points, const int64_t *heights, int N, int k,
+                     bdeg_u128 *nvol, int32_t *tie, uint64_t *cells, bdeg_prune_stats *ps) {
+  const int W = P.W, d = P.d;
+  const std::vector<uint64_t> &items = P.items;
+  const std::vector<uint16_t> &chunk_start = P.chunk_start;
+  const std::vector<uint8_t> &run_lo = P.run_lo, &run_hi = P.run_hi;
+  const uint32_t *off = P.off;
+  const uint64_t cap_units = P.cap_units;
+  int rc = BDEG_OK;
   Job job;
   points_job(job, points, heights, N, k, 0, 0); // no units: they come from the prefixes
   if ((rc = job_upload(job)) || (rc = job_launch_pre(job, D->stream))) return rc;
@@ -814,7 +882,7 @@ int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32
       hipMalloc((void **)&d_raw, cap_units * sizeof(Tile)) != hipSuccess ||
       hipMalloc((void **)&d_units, cap_units * sizeof(Tile)) != hipSuccess ||
       hipMalloc((void **)&d_pc, sizeof(PruneCounters)) != hipSuccess ||
-      hipMalloc((void **)&d_off, sizeof off) != hipSuccess || hipMalloc((void **)&d_bcnt, sizeof off) != hipSuccess ||
+      hipMalloc((void **)&d_off, 64 * sizeof(uint32_t)) != hipSuccess || hipMalloc((void **)&d_bcnt, 64 * sizeof(uint32_t)) != hipSuccess ||
       hipMalloc((void **)&d_cs, chunk_start.size() * sizeof(uint16_t)) != hipSuccess ||
       hipMalloc((void **)&d_rlo, run_lo.size()) != hipSuccess || hipMalloc((void **)&d_rhi, run_hi.size()) != hipSuccess) {
     cleanup();
@@ -829,8 +897,8 @@ int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32
   if (hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(uint64_t), hipMemcpyHostToDevice, D->stream) !=
           hipSuccess ||
       hipMemcpyAsync(d_pc, &pc, sizeof pc, hipMemcpyHostToDevice, D->stream) != hipSuccess ||
-      hipMemcpyAsync(d_off, off, sizeof off, hipMemcpyHostToDevice, D->stream) != hipSuccess ||
-      hipMemsetAsync(d_bcnt, 0, sizeof off, D->stream) != hipSuccess ||
+      hipMemcpyAsync(d_off, off, 64 * sizeof(uint32_t), hipMemcpyHostToDevice, D->stream) != hipSuccess ||
+      hipMemsetAsync(d_bcnt, 0, 64 * sizeof(uint32_t), D->stream) != hipSuccess ||
       hipMemcpyAsync(d_cs, chunk_start.data(), chunk_start.size() * sizeof(uint16_t), hipMemcpyHostToDevice,
                      D->stream) != hipSuccess ||
       hipMemcpyAsync(d_rlo, run_lo.data(), run_lo.size(), hipMemcpyHostToDevice, D->stream) != hipSuccess ||
@@ -898,6 +966,23 @@ int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32
   }
   cleanup();
   return rc;
+}
+
+
+} // namespace bdeg
+
+int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, int32_t width,
+                            bdeg_u128 *nvol, int32_t *tie, uint64_t *cells, bdeg_prune_stats *ps) {
+  if (!nvol || !tie) return BDEG_E_ARG;
+  int rc = check_points(points, heights, N, k);
+  if (rc) return rc;
+  PrunePlan P;
+  if ((rc = prune_plan(N, k, width, P))) return rc;
+  int st;
+  Device *D = device_get(&st);
+  if (!D) return st;
+  std::lock_guard<std::mutex> lk(D->mu);
+  return prune_run(D, P, points, heights, N, k, nvol, tie, cells, ps);
 }
 
 int bdeg_cells_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k, uint64_t rank_lo,

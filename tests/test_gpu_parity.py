@@ -9,6 +9,7 @@
   workloads (``tests/golden``).
 """
 import json
+import math
 import os
 
 import numpy as np
@@ -416,6 +417,31 @@ def test_cfg4_large_36():
     say("cfg4")
     g = bd.degree(gen.cfg4_system().A, seed=1, lift_bits=24)
     assert (g["k"], g["comps"], g["nvol"]) == (e["k"], e["comps"], e["nvol"])
+
+
+def test_degree_cost_model_prunes_large_systems():
+    """A one-shot system of at least BDEG_PRUNE_MIN_CANDIDATES candidates goes
+    through the prefix-pruned enumeration (BDEG_F_PRUNED) with the plain
+    path's result, attempts and cells included; the plain path here is the
+    lanes-as-points schedule, which never prunes.  12-bit heights make ties
+    and redraws likely."""
+    A = gen.cfg4_system().A
+    assert math.comb(37, 11) >= bd.PRUNE_MIN_CANDIDATES
+    for bits in (24, 12):
+        say("cost model", bits)
+        g = bd.degree(A, seed=3, lift_bits=bits, check=False)
+        bd.set_schedule(bd.SCHED_POINTS)
+        try:
+            p = bd.degree(A, seed=3, lift_bits=bits, check=False)
+        finally:
+            bd.set_schedule(bd.SCHED_AUTO)
+        assert g["flags"] & bd.BDEG_F_PRUNED and not p["flags"] & bd.BDEG_F_PRUNED
+        assert (g["status"], g["k"], g["comps"], g["nvol"], g["attempts"], g["cells"]) == \
+            (p["status"], p["k"], p["comps"], p["nvol"], p["attempts"], p["cells"])
+        if g["status"] == 0:
+            assert g["nvol"] == _golden("cfg4")[0]["nvol"]
+    small = bd.degree(gen.cfg2_system().A, seed=3, lift_bits=20)
+    assert not small["flags"] & bd.BDEG_F_PRUNED
 
 
 def test_cfg3_batch_4096():

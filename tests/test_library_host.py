@@ -45,7 +45,8 @@ def test_binding_constants_equal_the_header():
         "BDEG_MAX_N": bd.MAX_N, "BDEG_MAX_K": bd.MAX_K, "BDEG_MAX_ATTEMPTS": bd.MAX_ATTEMPTS,
         "BDEG_PIVOT_MAX_K": bd.PIVOT_MAX_K, "BDEG_PRUNE_MAX_PREFIXES": bd.PRUNE_MAX_PREFIXES,
         "BDEG_NOALLOC_MAX_UNITS": bd.NOALLOC_MAX_UNITS, "BDEG_SCHED_AUTO": bd.SCHED_AUTO,
-        "BDEG_SCHED_POINTS": bd.SCHED_POINTS,
+        "BDEG_SCHED_POINTS": bd.SCHED_POINTS, "BDEG_F_PRUNED": bd.BDEG_F_PRUNED,
+        "BDEG_PRUNE_MIN_CANDIDATES": bd.PRUNE_MIN_CANDIDATES,
     }
     for name, v in binding.items():
         assert name in defs, name
