@@ -48,9 +48,9 @@ TRAFFIC = {
     "sources": ("enum_device.hpp", "enum_dense.hpp", "exact_div.hpp", "kernels_k10.hip", "runtime.cpp",
                 "bdeg_internal.hpp", "lifting.hpp"),
     "table": os.path.join("tuning", "gfx950.json"),
-    "sha256": "79368f51088b87163eed565ec62e5cfb696d0ea7a38a4a69fdea4a21720d432d",
-    "fetch_kib": 32422.8, "fetch_scale": 262144.0 / 131087.75,
-    "write_kib": 829563.6, "write_scale": 262144.0 / 262144.0,
+    "sha256": "03a74178b7f80b54192309216c0d557b91fa9da1505808842a04eb6324b91d10",
+    "fetch_kib": 31881.77, "fetch_scale": 262144.0 / 131088.44,
+    "write_kib": 839970.56, "write_scale": 262144.0 / 262144.0,
 }
 
 
