@@ -117,7 +117,9 @@ struct CellSink {
 
 // ------------------------------------------------------------ cell walk (kernels_pivot*.hip)
 constexpr int PIVOT_MAX_K = BDEG_PIVOT_MAX_K; // deepest k of the cell walk
-constexpr int PIVOT_CHAIN_STEPS = 4;           // chain steps after one claimed cell
+constexpr int PIVOT_DFS_MAX = 32;              // cells reached by pivots from one claimed cell, at most
+constexpr int PIVOT_CREDIT_CELLS = 64;         // a wave takes the level's room in chunks of this many cells
+constexpr int PIVOT_CLAIM_BATCH = 4;           // listed cells a wave claims at once in wide levels
 constexpr uint32_t PIVOT_TIE = 1;       // a non-generic lower face was met
 constexpr uint32_t PIVOT_ERR_FULL = 2;  // hash set or work list out of room
 constexpr uint32_t PIVOT_ERR_STATE = 4; // a listed cell is not a lower facet (bad start cell)
@@ -129,7 +131,7 @@ struct PivotCounters {
   uint32_t pad;
   unsigned long long vol_lo, vol_hi; // sum of |D| over processed cells (128-bit)
   unsigned long long cells;          // processed cells
-  uint32_t chained;                  // chain steps claimed in the current level
+  uint32_t committed; // the level's insertions, plus k + 1 per committed cell not yet processed
   uint32_t pad2;
 };
 
@@ -143,7 +145,7 @@ struct PivotArgs {
   uint32_t cap_list;
   uint64_t *table;    // hash set of cells (0 = empty), power-of-two size
   uint64_t table_mask;
-  uint32_t chain_budget; // chain steps the list's room allows in this level
+  uint32_t room;      // cells the set and the list can take in this level (bounds `committed`)
   PivotCounters *cnt;
 };
 typedef void (*PivotFn)(PivotArgs);

@@ -207,25 +207,28 @@ int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k,
         hipMemcpyAsync(b.cnt, &c0, sizeof c0, hipMemcpyHostToDevice, D->stream) != hipSuccess)
       return BDEG_E_DEVICE;
     uint32_t first = 0, count = 1;
-    uint64_t in_set = 1; // cells in the set: the listed ones and the chained ones
+    uint64_t in_set = 1; // cells in the set: the listed ones and those reached by pivots
     PivotCounters c{};
     bool regrow = false;
     while (count > 0) {
-      // every cell processed in this level (listed or chained) inserts at most
-      // k + 1 new cells into the set and the list; room for the level's own
-      // cells and as many again for chained ones, and chain steps limited to
-      // what is left, keep the list within its capacity and the set at most
-      // half full
+      // every cell processed in this level (listed, or reached by a pivot)
+      // inserts at most k + 1 new cells into the set and the list; room for
+      // the level's own cells twice over, and pivots reserved only within
+      // the room left, keep the list within its capacity and the set at
+      // most half full
       const uint64_t tail0 = (uint64_t)first + count;
       rc = grow(D, b, a, in_set + 2 * (uint64_t)count * (k + 1), (uint32_t)tail0);
       if (rc) return rc;
       a.first = first;
       a.count = count;
-      const uint64_t steps = (b.cap - in_set) / (uint64_t)(k + 1);
-      a.chain_budget = steps > count ? (uint32_t)std::min<uint64_t>(steps - count, 0xFFFFFFFFull) : 0u;
-      const uint32_t zero = 0;
+      // the level's room in cells; the listed cells are committed with k + 1
+      // insertions each, and each processed cell gives back what it did not
+      // insert, so `chained` ends as the number of cells the level inserted
+      a.room = (uint32_t)(b.cap - in_set);
+      const uint32_t zero = 0, committed = count * (uint32_t)(k + 1);
       if (hipMemcpyAsync(&b.cnt->next, &zero, sizeof zero, hipMemcpyHostToDevice, D->stream) != hipSuccess ||
-          hipMemcpyAsync(&b.cnt->chained, &zero, sizeof zero, hipMemcpyHostToDevice, D->stream) != hipSuccess)
+          hipMemcpyAsync(&b.cnt->committed, &committed, sizeof committed, hipMemcpyHostToDevice, D->stream) !=
+              hipSuccess)
         return BDEG_E_DEVICE;
       rc = launch_pivot(D->stream, a, k, blocks);
       if (rc) return rc;
@@ -241,7 +244,8 @@ int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k,
         out.tie = true;
         return BDEG_OK;
       }
-      in_set += (uint64_t)(c.tail - tail0) + std::min<uint64_t>(c.chained, a.chain_budget);
+      if (c.committed < c.tail - tail0 || c.committed > a.room) return BDEG_E_DEVICE; // (room accounting)
+      in_set += c.committed;
       first += count;
       count = c.tail - first;
     }

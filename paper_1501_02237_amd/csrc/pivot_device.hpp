@@ -71,15 +71,50 @@ __device__ __forceinline__ bool set_insert(const PivotArgs &a, uint64_t m) {
 template <int K>
 __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
   const int lane = (int)(threadIdx.x & 63);
+  const int wv = (int)(threadIdx.x >> 6);
   uint64_t vol = 0, cells = 0; // this wave's cells (uniform across the wave)
+  uint32_t credit = 0;         // room the wave holds (uniform), in insertions
+  // the depth-first pivots of each wave: per depth the rows reserved, the
+  // point entering across each reserved row (lane = row), and how the cell
+  // at that depth was entered (row and the point that left)
+  __shared__ uint8_t s_u[4][PIVOT_DFS_MAX + 1][64];
+  __shared__ uint32_t s_res[4][PIVOT_DFS_MAX + 1];
+  __shared__ uint8_t s_row[4][PIVOT_DFS_MAX + 1], s_left[4][PIVOT_DFS_MAX + 1];
+  // cells one claimed cell may reach by pivots: few while the level has
+  // fewer cells than the grid has waves (long serial runs would hold the
+  // level up), more as the level widens
+  const uint32_t waves = gridDim.x * 4u;
+  const bool wide = a.count >= 16u * waves;
+  const uint32_t item_reach = wide ? (uint32_t)PIVOT_DFS_MAX : a.count >= 2u * waves ? 8u : 2u;
+  // cells a wave claims at once, and its list appends collected in LDS:
+  // the shared counters then take one atomic per several cells
+  const uint32_t batch = wide ? (uint32_t)PIVOT_CLAIM_BATCH : 1u;
+  __shared__ uint64_t s_buf[4][64];
+  uint32_t nbuf = 0; // (uniform)
+  const auto flush = [&]() {
+    const uint32_t pos = (uint32_t)prl((int32_t)atomicAdd(&a.cnt->tail, lane == 0 ? nbuf : 0u), 0);
+    if ((uint32_t)lane < nbuf) {
+      if (pos + (uint32_t)lane < a.cap_list)
+        a.list[pos + lane] = s_buf[wv][lane];
+      else
+        atomicOr(&a.cnt->flags, PIVOT_ERR_FULL);
+    }
+    nbuf = 0;
+  };
+  uint32_t next_item = 0, claimed = 0;
   for (;;) {
-    // Every lane takes part in the claim (lane 0 adds one, the others zero)
+    // Every lane takes part in the claim (lane 0 adds, the others add zero)
     // and lane 0's result is read by index.  A claim made under a lane-0 branch
     // leaves a lane-dependent value at the loop header; the compiler may then
     // split the loop so that lanes 1..63 reach the broadcast without lane 0
     // and never leave it.
-    const uint32_t claim = atomicAdd(&a.cnt->next, lane == 0 ? 1u : 0u);
-    const uint32_t item = (uint32_t)__builtin_amdgcn_readlane((int32_t)claim, 0);
+    if (claimed == 0) {
+      const uint32_t claim = atomicAdd(&a.cnt->next, lane == 0 ? batch : 0u);
+      next_item = (uint32_t)__builtin_amdgcn_readlane((int32_t)claim, 0);
+      claimed = batch;
+    }
+    const uint32_t item = next_item++;
+    claimed--;
     if (item >= a.count) break;
     const uint64_t C = a.list[a.first + item];
     const int v0 = __builtin_ctzll(C);
@@ -129,84 +164,138 @@ __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
       if (lane == 0) atomicOr(&a.cnt->flags, PIVOT_ERR_STATE);
       continue;
     }
-    // the cell, then a chain of neighbours: each one is reached by one pivot
-    // of the tableau instead of a new elimination
+    // The cell, then cells reached from it by pivots of the tableau instead
+    // of new eliminations: depth first over new neighbours across facets
+    // t < k (they keep the base point), returning to a cell by the inverse
+    // pivot, at most `reach` cells per claimed cell.  A new neighbour that is
+    // not reserved for a pivot goes to the list.
     int32_t D = prev;
     uint64_t Cc = C;
-    for (int hop = 0;; hop++) {
-      const bool neg = D < 0;
-      const bool in_c = (Cc >> lane) & 1;
-      // height above the cell's hyperplane, times |D|
-      const int64_t s_raw = (int64_t)H1 * ((int64_t)1 << 31) + (int64_t)(uint32_t)H0;
-      const int64_t S = neg ? -s_raw : s_raw;
-      const bool other = valid && !in_c;
-      const uint64_t below = pballot(other && S < 0), on = pballot(other && S == 0);
-      if (below) { // not a lower facet: the start cell was wrong, or a bug
-        if (lane == 0) atomicOr(&a.cnt->flags, PIVOT_ERR_STATE);
+    uint32_t reach = item_reach;
+    int depth = 0;
+    bool fresh_cell = true; // false: back at a cell by the inverse pivot
+    for (;;) {
+      if (fresh_cell) {
+        const bool neg = D < 0;
+        const bool in_c = (Cc >> lane) & 1;
+        // height above the cell's hyperplane, times |D|
+        const int64_t s_raw = (int64_t)H1 * ((int64_t)1 << 31) + (int64_t)(uint32_t)H0;
+        const int64_t S = neg ? -s_raw : s_raw;
+        const bool other = valid && !in_c;
+        const uint64_t below = pballot(other && S < 0), on = pballot(other && S == 0);
+        if (below) { // not a lower facet: the start cell was wrong, or a bug
+          if (lane == 0) atomicOr(&a.cnt->flags, PIVOT_ERR_STATE);
+          break;
+        }
+        if (on && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE);
+        vol += (uint64_t)(neg ? -(int64_t)D : (int64_t)D);
+        cells++;
+        // barycentric coordinate of the base point, times D
+        int64_t sum = 0;
+#pragma unroll
+        for (int t = 0; t < K; t++) sum += x[t];
+        const int64_t c0 = (int64_t)D - sum;
+        // facets: opposite the point pivoted at step t (row t), then opposite
+        // v0; lane t keeps the neighbour across facet t and the point entering
+        uint64_t mine = 0;
+        int my_u = 0;
+#pragma unroll
+        for (int t = 0; t <= K; t++) {
+          const int64_t c = t < K ? (int64_t)x[t] : c0;
+          const int64_t cs = neg ? -c : c; // lambda * |D|
+          const bool beyond = other && cs < 0;
+          const RatioMin rm = ratio_min(beyond ? S : 0, beyond ? (int32_t)(-cs) : 0);
+          const int u = rm.lane;
+          if ((rm.lanes & (rm.lanes - 1)) && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE); // equal minima
+          if (u >= 0) { // (none: the facet is on the boundary of the hull)
+            const int v = t < K ? pivlane[t] : v0;
+            if (lane == t) {
+              mine = (Cc & ~(1ull << v)) | (1ull << u);
+              my_u = u;
+            }
+          }
+        }
+        // lane t inserts the neighbour across facet t: all probes in one round
+        const bool fresh = mine && set_insert(a, mine);
+        // The level's room: `committed` holds the insertions made plus k + 1
+        // for every cell committed and not yet processed, plus what the
+        // waves hold as credit, and stays within a.room (the cells the set
+        // and the list can still take).  This cell's unused insertions go
+        // to the wave's credit; new neighbours across facets t < k are
+        // reserved for pivots at k + 1 each, while this claimed cell's reach
+        // and the credit allow.  A wave short of credit takes a chunk of the
+        // level's room (one shared atomic per many cells).
+        const uint64_t fb = pballot(fresh);
+        const uint64_t fr = fb & ((1ull << K) - 1);
+        credit += (uint32_t)(K + 1 - __builtin_popcountll(fb));
+        const uint32_t want = min((uint32_t)__builtin_popcountll(fr), reach);
+        if (want * (K + 1) > credit) {
+          const uint32_t ask = max(want * (K + 1) - credit, (uint32_t)(PIVOT_CREDIT_CELLS * (K + 1)));
+          const uint32_t before =
+              (uint32_t)prl((int32_t)atomicAdd(&a.cnt->committed, lane == 0 ? ask : 0u), 0);
+          const uint32_t fit = before >= a.room ? 0u : min(ask, a.room - before);
+          if (fit < ask && lane == 0) atomicSub(&a.cnt->committed, ask - fit);
+          credit += fit;
+        }
+        const uint32_t got = min(want, credit / (uint32_t)(K + 1));
+        credit -= got * (uint32_t)(K + 1);
+        constexpr uint32_t chunk = (uint32_t)(PIVOT_CREDIT_CELLS * (K + 1));
+        if (credit > 4 * chunk) { // hand back what the wave does not need
+          if (lane == 0) atomicSub(&a.cnt->committed, credit - chunk);
+          credit = chunk;
+        }
+        uint64_t R = 0;
+        {
+          uint64_t f = fr;
+          for (uint32_t i = 0; i < got; i++) {
+            const uint64_t low = f & (~f + 1);
+            R |= low;
+            f ^= low;
+          }
+        }
+        reach -= got;
+        // the other new neighbours go to the list (through the wave's buffer)
+        const uint64_t lm = fb & ~R;
+        const uint32_t nl = (uint32_t)__builtin_popcountll(lm);
+        if (nbuf + nl > 64u) flush();
+        if ((lm >> lane) & 1) s_buf[wv][nbuf + __builtin_popcountll(lm & ((1ull << lane) - 1))] = mine;
+        nbuf += nl;
+        if ((R >> lane) & 1) s_u[wv][depth][lane] = (uint8_t)my_u;
+        if (lane == 0) s_res[wv][depth] = (uint32_t)R;
+      }
+      // next: the deepest cell's next reserved neighbour, else back up one
+      const uint32_t Rd = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)s_res[wv][depth]);
+      int tp, up;
+      if (Rd) {
+        tp = __builtin_ctz(Rd);
+        up = __builtin_amdgcn_readfirstlane((int32_t)s_u[wv][depth][tp]);
+        if (lane == 0) s_res[wv][depth] = Rd & (Rd - 1);
+      } else if (depth > 0) {
+        tp = __builtin_amdgcn_readfirstlane((int32_t)s_row[wv][depth]);
+        up = __builtin_amdgcn_readfirstlane((int32_t)s_left[wv][depth]);
+      } else {
         break;
       }
-      if (on && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE);
-      vol += (uint64_t)(neg ? -(int64_t)D : (int64_t)D);
-      cells++;
-      // barycentric coordinate of the base point, times D
-      int64_t sum = 0;
-#pragma unroll
-      for (int t = 0; t < K; t++) sum += x[t];
-      const int64_t c0 = (int64_t)D - sum;
-      // facets: opposite the point pivoted at step t (row t), then opposite v0;
-      // lane t keeps the neighbour across facet t
-      uint64_t mine = 0;
-#pragma unroll
-      for (int t = 0; t <= K; t++) {
-        const int64_t c = t < K ? (int64_t)x[t] : c0;
-        const int64_t cs = neg ? -c : c; // lambda * |D|
-        const bool beyond = other && cs < 0;
-        const RatioMin rm = ratio_min(beyond ? S : 0, beyond ? (int32_t)(-cs) : 0);
-        const int u = rm.lane;
-        if ((rm.lanes & (rm.lanes - 1)) && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE); // equal minima
-        if (u >= 0) { // (none: the facet is on the boundary of the hull)
-          const int v = t < K ? pivlane[t] : v0;
-          if (lane == t) mine = (Cc & ~(1ull << v)) | (1ull << u);
-        }
-      }
-      // lane t inserts the neighbour across facet t: all probes in one round
-      const bool fresh = mine && set_insert(a, mine);
-      // the chain goes on into the first new neighbour across a facet t < k
-      // (same base point) while the level's room allows
-      const uint64_t fr = pballot(fresh) & ((1ull << K) - 1);
-      int tc = -1;
-      if (fr && hop < PIVOT_CHAIN_STEPS) { // (longer chains serialise a level)
-        const uint32_t claim = atomicAdd(&a.cnt->chained, lane == 0 ? 1u : 0u);
-        if ((uint32_t)prl((int32_t)claim, 0) < a.chain_budget) tc = __builtin_ctzll(fr);
-      }
-      if (fresh && lane != tc) {
-        const uint32_t pos = atomicAdd(&a.cnt->tail, 1u);
-        if (pos < a.cap_list)
-          a.list[pos] = mine;
-        else
-          atomicOr(&a.cnt->flags, PIVOT_ERR_FULL);
-      }
-      if (tc < 0) break;
-      // pivot: the point of row tc leaves, u enters; with e = x_tc(u),
-      // x_r <- (e x_r - x_r(u) x_tc) / D for r != tc, row tc stays, D <- e
-      const uint64_t nb = ((uint64_t)(uint32_t)prl((int32_t)(mine >> 32), tc) << 32) |
-                          (uint32_t)prl((int32_t)(uint32_t)mine, tc);
-      const int u = __builtin_ctzll(nb & ~Cc);
+      // pivot: the point of row tp leaves, point up enters; with e = x_tp(up),
+      // x_r <- (e x_r - x_r(up) x_tp) / D for r != tp, row tp stays, D <- e.
+      // Applied with the point that left, it restores the tableau before.
       int32_t pc[K];
 #pragma unroll
-      for (int r = 0; r < K; r++) pc[r] = prl(x[r], u);
-      const int32_t ph1 = prl(H1, u), ph0 = prl(H0, u);
+      for (int r = 0; r < K; r++) pc[r] = prl(x[r], up);
+      const int32_t ph1 = prl(H1, up), ph0 = prl(H0, up);
       int32_t e = 1, xt = 0;
+      int vout = 0;
 #pragma unroll
       for (int r = 0; r < K; r++)
-        if (r == tc) {
+        if (r == tp) {
           e = pc[r];
           xt = x[r];
+          vout = pivlane[r];
         }
       const Div dv = make_div(D);
 #pragma unroll
       for (int r = 0; r < K; r++)
-        if (r != tc) x[r] = exdiv32((int64_t)e * x[r] - (int64_t)pc[r] * xt, dv);
+        if (r != tp) x[r] = exdiv32((int64_t)e * x[r] - (int64_t)pc[r] * xt, dv);
       const int64_t A = (int64_t)e * H1 - (int64_t)ph1 * xt;
       const int64_t B = (int64_t)e * H0 - (int64_t)ph0 * xt;
       const int64_t h = exdiv_split(A, B, dv);
@@ -214,11 +303,26 @@ __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
       H0 = (int32_t)((uint32_t)h & PIVOT_LOW31);
 #pragma unroll
       for (int r = 0; r < K; r++)
-        if (r == tc) pivlane[r] = u;
+        if (r == tp) pivlane[r] = up;
       D = e;
-      Cc = nb;
+      Cc = (Cc & ~(1ull << vout)) | (1ull << up);
+      if (Rd) { // down into the reserved neighbour
+        depth++;
+        if (lane == 0) {
+          s_row[wv][depth] = (uint8_t)tp;
+          s_left[wv][depth] = (uint8_t)vout;
+        }
+        fresh_cell = true;
+      } else { // back up
+        depth--;
+        fresh_cell = false;
+      }
     }
   }
+  if (nbuf) flush();
+  // the credit goes back to the level's room, so that `committed` ends as
+  // the number of cells the level inserted
+  if (lane == 0 && credit) atomicSub(&a.cnt->committed, credit);
   // the wave's tallies (uniform values) in one update
   if (lane == 0 && cells) {
     const unsigned long long old = atomicAdd(&a.cnt->vol_lo, (unsigned long long)vol);
