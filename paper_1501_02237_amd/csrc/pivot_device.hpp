@@ -68,8 +68,10 @@ __device__ __forceinline__ bool set_insert(const PivotArgs &a, uint64_t m) {
   return false;
 }
 
+// (at least 5 waves per SIMD: at k = 20..24 that spills a few VGPRs, and the
+// walk of k = 22 is faster for it than at 4 waves without spills)
 template <int K>
-__global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) pivot_kernel(PivotArgs a) {
   const int lane = (int)(threadIdx.x & 63);
   const int wv = (int)(threadIdx.x >> 6);
   uint64_t vol = 0, cells = 0; // this wave's cells (uniform across the wave)
@@ -101,6 +103,49 @@ __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
     }
     nbuf = 0;
   };
+  // the tableau (lane j = point j), kept from one claimed cell to the next
+  const bool valid = lane < a.N;
+  int32_t x[K];
+  int32_t H1 = 0, H0 = 0;
+  int pivlane[K]; // the point pivoted at step t (row t)
+  int32_t D = 1;
+  uint64_t Cc = 0;
+  int v0 = 0;
+  bool have = false; // the tableau holds the last claimed cell
+  // pivot: the point of row tp leaves, point up enters; with e = x_tp(up),
+  // x_r <- (e x_r - x_r(up) x_tp) / D for r != tp, row tp stays, D <- e.
+  // Applied with the point that left, it restores the tableau before.
+  // Returns the point that left.
+  const auto pivot = [&](int tp, int up) {
+    int32_t pc[K];
+#pragma unroll
+    for (int r = 0; r < K; r++) pc[r] = prl(x[r], up);
+    const int32_t ph1 = prl(H1, up), ph0 = prl(H0, up);
+    int32_t e = 1, xt = 0;
+    int vout = 0;
+#pragma unroll
+    for (int r = 0; r < K; r++)
+      if (r == tp) {
+        e = pc[r];
+        xt = x[r];
+        vout = pivlane[r];
+      }
+    const Div dv = make_div(D);
+#pragma unroll
+    for (int r = 0; r < K; r++)
+      if (r != tp) x[r] = exdiv32((int64_t)e * x[r] - (int64_t)pc[r] * xt, dv);
+    const int64_t A = (int64_t)e * H1 - (int64_t)ph1 * xt;
+    const int64_t B = (int64_t)e * H0 - (int64_t)ph0 * xt;
+    const int64_t h = exdiv_split(A, B, dv);
+    H1 = (int32_t)(h >> 31);
+    H0 = (int32_t)((uint32_t)h & PIVOT_LOW31);
+#pragma unroll
+    for (int r = 0; r < K; r++)
+      if (r == tp) pivlane[r] = up;
+    D = e;
+    Cc = (Cc & ~(1ull << vout)) | (1ull << up);
+    return vout;
+  };
   uint32_t next_item = 0, claimed = 0;
   for (;;) {
     // Every lane takes part in the claim (lane 0 adds, the others add zero)
@@ -117,61 +162,92 @@ __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
     claimed--;
     if (item >= a.count) break;
     const uint64_t C = a.list[a.first + item];
-    const int v0 = __builtin_ctzll(C);
-    const bool valid = lane < a.N;
-    // lane j's column: spatial differences and the split height difference
-    int32_t x[K];
-    int32_t H1 = 0, H0 = 0;
-    if (valid) {
+    // From the last claimed cell by pivots when both keep the base point and
+    // differ in a few points (consecutive list entries are mostly siblings),
+    // else a new elimination.  A pivot with a zero entry (no point of the
+    // new cell can replace a leaving one in its row) falls back too.
+    bool elim = true;
+    if (have && ((C >> v0) & 1) && __builtin_popcountll(Cc & ~C) <= PIVOT_SWAPS) {
+      uint64_t outm = Cc & ~C, inm = C & ~Cc;
+      bool ok = true;
+      while (outm) {
+        const int v = __builtin_ctzll(outm);
+        outm &= outm - 1;
+        int tp = 0;
+        int32_t xr = 0;
 #pragma unroll
-      for (int r = 0; r < K; r++) x[r] = a.pts[lane * K + r] - a.pts[v0 * K + r];
-      const int64_t y = a.hts[lane] - a.hts[v0];
-      H1 = (int32_t)(y >> 31);
-      H0 = (int32_t)((uint32_t)y & PIVOT_LOW31);
-    } else {
-#pragma unroll
-      for (int r = 0; r < K; r++) x[r] = 0;
+        for (int r = 0; r < K; r++)
+          if (pivlane[r] == v) {
+            tp = r;
+            xr = x[r];
+          }
+        const uint64_t cand = pballot(((inm >> lane) & 1) && xr != 0) & inm;
+        if (!cand) {
+          ok = false;
+          break;
+        }
+        const int u = __builtin_ctzll(cand);
+        inm &= ~(1ull << u);
+        (void)pivot(tp, u);
+      }
+      elim = !ok;
     }
-    uint64_t unused = C & ~(1ull << v0);
-    int pivlane[K];
-    int32_t prev = 1;
-    bool singular = false;
+    if (elim) {
+      v0 = __builtin_ctzll(C);
+      // lane j's column: spatial differences and the split height difference
+      H1 = H0 = 0;
+      if (valid) {
 #pragma unroll
-    for (int t = 0; t < K; t++) {
-      const uint64_t cand = pballot(((unused >> lane) & 1) && x[t] != 0) & unused;
-      singular |= cand == 0;
-      const int pl = cand ? __builtin_ctzll(cand) : v0; // (a singular cell is discarded below)
-      pivlane[t] = pl;
-      unused &= ~(1ull << pl);
-      int32_t pc[K];
+        for (int r = 0; r < K; r++) x[r] = a.pts[lane * K + r] - a.pts[v0 * K + r];
+        const int64_t y = a.hts[lane] - a.hts[v0];
+        H1 = (int32_t)(y >> 31);
+        H0 = (int32_t)((uint32_t)y & PIVOT_LOW31);
+      } else {
 #pragma unroll
-      for (int r = 0; r < K; r++) pc[r] = prl(x[r], pl);
-      const int32_t ph1 = prl(H1, pl), ph0 = prl(H0, pl);
-      const int32_t p = cand ? pc[t] : 1;
-      const Div dv = make_div(prev);
-      const int32_t xt = x[t];
+        for (int r = 0; r < K; r++) x[r] = 0;
+      }
+      uint64_t unused = C & ~(1ull << v0);
+      int32_t prev = 1;
+      bool singular = false;
 #pragma unroll
-      for (int r = 0; r < K; r++)
-        if (r != t) x[r] = exdiv32((int64_t)p * x[r] - (int64_t)pc[r] * xt, dv);
-      const int64_t A = (int64_t)p * H1 - (int64_t)ph1 * xt;
-      const int64_t B = (int64_t)p * H0 - (int64_t)ph0 * xt;
-      const int64_t h = exdiv_split(A, B, dv);
-      H1 = (int32_t)(h >> 31);
-      H0 = (int32_t)((uint32_t)h & PIVOT_LOW31);
-      prev = p;
-    }
-    if (singular) { // a listed cell must be a full simplex
-      if (lane == 0) atomicOr(&a.cnt->flags, PIVOT_ERR_STATE);
-      continue;
+      for (int t = 0; t < K; t++) {
+        const uint64_t cand = pballot(((unused >> lane) & 1) && x[t] != 0) & unused;
+        singular |= cand == 0;
+        const int pl = cand ? __builtin_ctzll(cand) : v0; // (a singular cell is discarded below)
+        pivlane[t] = pl;
+        unused &= ~(1ull << pl);
+        int32_t pc[K];
+#pragma unroll
+        for (int r = 0; r < K; r++) pc[r] = prl(x[r], pl);
+        const int32_t ph1 = prl(H1, pl), ph0 = prl(H0, pl);
+        const int32_t p = cand ? pc[t] : 1;
+        const Div dv = make_div(prev);
+        const int32_t xt = x[t];
+#pragma unroll
+        for (int r = 0; r < K; r++)
+          if (r != t) x[r] = exdiv32((int64_t)p * x[r] - (int64_t)pc[r] * xt, dv);
+        const int64_t A = (int64_t)p * H1 - (int64_t)ph1 * xt;
+        const int64_t B = (int64_t)p * H0 - (int64_t)ph0 * xt;
+        const int64_t h = exdiv_split(A, B, dv);
+        H1 = (int32_t)(h >> 31);
+        H0 = (int32_t)((uint32_t)h & PIVOT_LOW31);
+        prev = p;
+      }
+      if (singular) { // a listed cell must be a full simplex
+        if (lane == 0) atomicOr(&a.cnt->flags, PIVOT_ERR_STATE);
+        have = false;
+        continue;
+      }
+      D = prev;
+      Cc = C;
     }
     // The cell, then cells reached from it by pivots of the tableau instead
     // of new eliminations: depth first over new neighbours across facets
     // t < k (they keep the base point), returning to a cell by the inverse
     // pivot, at most `reach` cells per claimed cell.  A new neighbour that is
     // not reserved for a pivot goes to the list.
-    int32_t D = prev;
-    uint64_t Cc = C;
     uint32_t reach = item_reach;
+    have = true; // (cleared when the cell is found not to be a lower facet)
     int depth = 0;
     bool fresh_cell = true; // false: back at a cell by the inverse pivot
     for (;;) {
@@ -185,6 +261,7 @@ __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
         const uint64_t below = pballot(other && S < 0), on = pballot(other && S == 0);
         if (below) { // not a lower facet: the start cell was wrong, or a bug
           if (lane == 0) atomicOr(&a.cnt->flags, PIVOT_ERR_STATE);
+          have = false;
           break;
         }
         if (on && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE);
@@ -276,36 +353,7 @@ __global__ void __launch_bounds__(256) pivot_kernel(PivotArgs a) {
       } else {
         break;
       }
-      // pivot: the point of row tp leaves, point up enters; with e = x_tp(up),
-      // x_r <- (e x_r - x_r(up) x_tp) / D for r != tp, row tp stays, D <- e.
-      // Applied with the point that left, it restores the tableau before.
-      int32_t pc[K];
-#pragma unroll
-      for (int r = 0; r < K; r++) pc[r] = prl(x[r], up);
-      const int32_t ph1 = prl(H1, up), ph0 = prl(H0, up);
-      int32_t e = 1, xt = 0;
-      int vout = 0;
-#pragma unroll
-      for (int r = 0; r < K; r++)
-        if (r == tp) {
-          e = pc[r];
-          xt = x[r];
-          vout = pivlane[r];
-        }
-      const Div dv = make_div(D);
-#pragma unroll
-      for (int r = 0; r < K; r++)
-        if (r != tp) x[r] = exdiv32((int64_t)e * x[r] - (int64_t)pc[r] * xt, dv);
-      const int64_t A = (int64_t)e * H1 - (int64_t)ph1 * xt;
-      const int64_t B = (int64_t)e * H0 - (int64_t)ph0 * xt;
-      const int64_t h = exdiv_split(A, B, dv);
-      H1 = (int32_t)(h >> 31);
-      H0 = (int32_t)((uint32_t)h & PIVOT_LOW31);
-#pragma unroll
-      for (int r = 0; r < K; r++)
-        if (r == tp) pivlane[r] = up;
-      D = e;
-      Cc = (Cc & ~(1ull << vout)) | (1ull << up);
+      const int vout = pivot(tp, up);
       if (Rd) { // down into the reserved neighbour
         depth++;
         if (lane == 0) {
