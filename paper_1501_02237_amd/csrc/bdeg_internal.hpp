@@ -120,7 +120,7 @@ constexpr int PIVOT_MAX_K = BDEG_PIVOT_MAX_K; // deepest k of the cell walk
 constexpr int PIVOT_DFS_MAX = 32;              // cells reached by pivots from one claimed cell, at most
 constexpr int PIVOT_CREDIT_CELLS = 64;         // a wave takes the level's room in chunks of this many cells
 constexpr int PIVOT_CLAIM_BATCH = 16;          // listed cells a wave claims at once in wide levels
-constexpr int PIVOT_SWAPS = 3;                 // points two claimed cells may differ in for pivots between them
+constexpr int PIVOT_SWAPS = 6;                 // points two claimed cells may differ in for pivots between them
 constexpr uint32_t PIVOT_TIE = 1;       // a non-generic lower face was met
 constexpr uint32_t PIVOT_ERR_FULL = 2;  // hash set or work list out of room
 constexpr uint32_t PIVOT_ERR_STATE = 4; // a listed cell is not a lower facet (bad start cell)

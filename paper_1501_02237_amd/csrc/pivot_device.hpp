@@ -162,12 +162,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     claimed--;
     if (item >= a.count) break;
     const uint64_t C = a.list[a.first + item];
-    // From the last claimed cell by pivots when both keep the base point and
-    // differ in a few points (consecutive list entries are mostly siblings),
-    // else a new elimination.  A pivot with a zero entry (no point of the
-    // new cell can replace a leaving one in its row) falls back too.
+    // From the last claimed cell by pivots when both differ in a few points
+    // (consecutive list entries are mostly siblings), else a new
+    // elimination.  A pivot with a zero entry (no point of the new cell can
+    // replace a leaving one in its row) falls back too.
     bool elim = true;
-    if (have && ((C >> v0) & 1) && __builtin_popcountll(Cc & ~C) <= PIVOT_SWAPS) {
+    if (have && __builtin_popcountll(Cc & ~C) <= PIVOT_SWAPS && (Cc & C)) {
+      if (!((C >> v0) & 1)) {
+        // new base w, a point of both cells: barycentric coordinates do not
+        // depend on the base, so row(w) becomes the old base's coordinate
+        // D - sum of the rows (a minor again) and the heights stay
+        const int w = __builtin_ctzll(Cc & C);
+        int64_t sum = 0;
+#pragma unroll
+        for (int r = 0; r < K; r++) sum += x[r];
+        const int32_t xb = valid ? (int32_t)((int64_t)D - sum) : 0;
+#pragma unroll
+        for (int r = 0; r < K; r++)
+          if (pivlane[r] == w) {
+            x[r] = xb;
+            pivlane[r] = v0;
+          }
+        v0 = w;
+      }
       uint64_t outm = Cc & ~C, inm = C & ~Cc;
       bool ok = true;
       while (outm) {
