@@ -48,7 +48,7 @@ TRAFFIC = {
     "sources": ("enum_device.hpp", "enum_dense.hpp", "exact_div.hpp", "kernels_k10.hip", "runtime.cpp",
                 "bdeg_internal.hpp", "lifting.hpp"),
     "table": os.path.join("tuning", "gfx950.json"),
-    "sha256": "03a74178b7f80b54192309216c0d557b91fa9da1505808842a04eb6324b91d10",
+    "sha256": "9c6a796339797578bd87de35f2939b340537a297a96147d19112d4b095818b4a",
     "fetch_kib": 31881.77, "fetch_scale": 262144.0 / 131088.44,
     "write_kib": 839970.56, "write_scale": 262144.0 / 262144.0,
 }
