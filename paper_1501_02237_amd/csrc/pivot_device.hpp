@@ -22,8 +22,13 @@
 //     the facet meets u first (the simplicial pivot).  No such point: the
 //     facet lies on the boundary of the convex hull.
 //   * New cells enter a device hash set of vertex masks (one CAS per probe);
-//     the first insertion appends the cell to the work list, so every cell is
-//     processed exactly once and adds |D| to the volume.
+//     the first insertion claims the cell, so every cell is processed exactly
+//     once and adds |D| to the volume.  A claimed cell is either reached at
+//     once by a pivot of the tableau (depth first, left again by the inverse
+//     pivot) or appended to the work list of the next level.
+//   * A wave goes from one listed cell to the next by a pivot per point that
+//     differs (consecutive entries are mostly siblings), moving the base
+//     point when needed, and eliminates afresh only when that fails.
 // A point on C's hyperplane, or two points with the same minimal ratio, means
 // the lifting is not generic: the walk reports a tie and the host redraws it.
 #pragma once
