@@ -93,9 +93,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
   const uint32_t waves = gridDim.x * 4u;
   const bool wide = a.count >= 16u * waves;
   const uint32_t item_reach = wide ? (uint32_t)PIVOT_DFS_MAX : a.count >= 2u * waves ? 8u : 2u;
-  // cells a wave claims at once, and its list appends collected in LDS:
+  // cells a wave claims at once (consecutive entries, so that the next one
+  // is mostly a few pivots away), and its list appends collected in LDS:
   // the shared counters then take one atomic per several cells
-  const uint32_t batch = wide ? (uint32_t)PIVOT_CLAIM_BATCH : 1u;
+  const uint32_t batch = wide ? (uint32_t)PIVOT_CLAIM_BATCH : 4u;
   __shared__ uint64_t s_buf[4][64];
   uint32_t nbuf = 0; // (uniform)
   const auto flush = [&]() {
