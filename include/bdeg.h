@@ -352,8 +352,10 @@ int bdeg_nvol_points_pruned(const int32_t *points, const int64_t *heights, int32
  *   cell_masks [cap] the cells, in no particular order (cap = 0: none copied);
  *   *n_cells, *nvol  number of cells and the sum of their normalized volumes;
  *   *tie             a non-generic lower face was met (results then invalid).
- * Device memory grows with the number of cells (16 bytes per cell in flight,
- * doubled on demand); BDEG_E_NOMEM beyond 2^31 cells.
+ * Device memory grows with the walk: before each breadth-first level the
+ * work list (8 bytes per cell) and the hash set (16 bytes per cell) are
+ * grown, by doubling, to the cells so far plus (k + 1) per cell of the level
+ * (twice that while it fits); BDEG_E_NOMEM when that passes 2^31 cells.
  */
 #define BDEG_PIVOT_MAX_K 24
 int bdeg_pivot_points(const int32_t *points, const int64_t *heights, int32_t N, int32_t k,

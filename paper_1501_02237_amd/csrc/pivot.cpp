@@ -213,11 +213,14 @@ int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k,
     while (count > 0) {
       // every cell processed in this level (listed, or reached by a pivot)
       // inserts at most k + 1 new cells into the set and the list; room for
-      // the level's own cells twice over, and pivots reserved only within
-      // the room left, keep the list within its capacity and the set at
-      // most half full
+      // the listed cells' worst case (twice over while that fits in 2^31
+      // cells, else a quarter more), and pivots reserved only within the
+      // room left, keep the list within its capacity and the set at most
+      // half full
       const uint64_t tail0 = (uint64_t)first + count;
-      rc = grow(D, b, a, in_set + 2 * (uint64_t)count * (k + 1), (uint32_t)tail0);
+      const uint64_t worst = (uint64_t)count * (k + 1);
+      const uint64_t roomy = in_set + 2 * worst;
+      rc = grow(D, b, a, roomy <= (1ull << 31) ? roomy : in_set + worst + worst / 4 + 65536, (uint32_t)tail0);
       if (rc) return rc;
       a.first = first;
       a.count = count;
