@@ -190,3 +190,50 @@ def test_degree_pivot_is_the_same_subdivision_as_degree(idx):
     e = bd.degree(A, seed=idx, lift_bits=bits, check=False)
     assert (p["status"], p["k"], p["comps"], p["nvol"], p["cells"], p["attempts"]) == \
         (e["status"], e["k"], e["comps"], e["nvol"], e["cells"], e["attempts"])
+
+
+@pytest.mark.parametrize("mk", ["2,8", "3,5", "4,4", "3,6"])
+def test_walk_from_extend_on_random_heights_table4(mk):
+    """The walk of a Table 4 system's points from Extend's facet on fully
+    random 30-bit heights (the origin is not lifted lowest, so the cells do
+    not share a point): wide levels, pivots and base changes between claimed
+    cells at scale.  The cells' normalized volumes sum to the volume of the
+    points' convex hull whatever the lifting, so comps * nvol is the paper's
+    degree (Section 2, the degree as a normalized volume)."""
+    m, k = map(int, mk.split(","))
+    kk, _, comps, P = bd.kernel_points(gen.master_space_matrix(m, k))
+    for attempt in range(3):
+        H = gen.random_heights(0x9D1 + 17 * m + k + 1000 * attempt, len(P), 30)
+        say("walk on random heights", mk, kk, len(P), attempt)
+        g = bd.pivot_points(P, H, 0)
+        if not g["tie"]:
+            break
+    assert not g["tie"]
+    assert comps * g["nvol"] == PAPER["table4_degrees"][mk]
+    assert 0 < g["cells"] <= g["nvol"]
+
+
+def test_walk_two_random_liftings_agree_off_the_pyramid():
+    """Table 4 configurations are pyramids (every point but the origin lies on
+    one hyperplane, so every cell holds the origin).  With the mirror image
+    -p of one point added the cells share no point, so the walk changes its
+    base between claimed cells.  The origin then lies inside, between p and
+    -p, so the hull is the pyramid over the same base with apex -p at twice
+    the origin's distance: its normalized volume is twice the configuration's,
+    2 * degree / comps, for any lifting."""
+    _, _, comps, P = bd.kernel_points(gen.master_space_matrix(3, 5))
+    deg = PAPER["table4_degrees"]["3,5"]
+    assert deg % comps == 0
+    P2 = np.vstack([P, -P[1:2]]).astype(np.int32)
+    vols = []
+    for seed in (0x9E1, 0x9E2):
+        for attempt in range(3):
+            H = gen.random_heights(seed + 1000 * attempt, len(P2), 30)
+            say("walk off the pyramid", seed, attempt, len(P2))
+            g = bd.pivot_points(P2, H, 0)
+            if not g["tie"]:
+                break
+        assert not g["tie"]
+        assert 0 < g["cells"] <= g["nvol"]
+        vols.append(g["nvol"])
+    assert vols[0] == vols[1] == 2 * deg // comps
