@@ -117,7 +117,7 @@ int normals_device(Device *D, const int32_t *d_pts, const int64_t *d_hts, int N,
 
 // Make room for `need` cells: a larger work list (the listed cells copied)
 // and a hash set of twice that many slots rebuilt from the old set (it holds
-// every cell, also the chained ones that never enter the list), so the set's
+// every cell, also those reached by pivots that never enter the list), so the set's
 // load stays at most 1/2.
 int grow(Device *D, WalkBuffers &b, PivotArgs &a, uint64_t need, uint32_t tail) {
   uint64_t cap = b.cap ? b.cap : (1ull << 20);
@@ -226,7 +226,7 @@ int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k,
       a.count = count;
       // the level's room in cells; the listed cells are committed with k + 1
       // insertions each, and each processed cell gives back what it did not
-      // insert, so `chained` ends as the number of cells the level inserted
+      // insert, so `committed` ends as the number of cells the level inserted
       a.room = (uint32_t)(b.cap - in_set);
       const uint32_t zero = 0, committed = count * (uint32_t)(k + 1);
       if (hipMemcpyAsync(&b.cnt->next, &zero, sizeof zero, hipMemcpyHostToDevice, D->stream) != hipSuccess ||
@@ -259,7 +259,7 @@ int walk(Device *D, const int32_t *points, const int64_t *heights, int N, int k,
     out.tie = false;
     out.nvol = ((u128)c.vol_hi << 64) | c.vol_lo;
     out.cells = c.cells;
-    if (cells_out) { // every cell is in the hash set (chained cells skip the list)
+    if (cells_out) { // every cell is in the hash set (cells reached by pivots skip the list)
       std::vector<uint64_t> slots(2 * b.cap);
       if (hipMemcpy(slots.data(), b.table, slots.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
         return BDEG_E_DEVICE;
