@@ -57,7 +57,7 @@ int launch_pivot(void *stream, const PivotArgs &a, int k, int blocks) {
 
 namespace dev {
 // Rebuild the hash set after it has grown: one thread per slot of the old
-// set (every cell, including the chained ones that never enter the list).
+// set (every cell, including those reached by pivots that never enter the list).
 __global__ void __launch_bounds__(256) pivot_rehash_kernel(PivotArgs a, const uint64_t *old, uint64_t n_old) {
   const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
   if (i < n_old && old[i]) (void)set_insert(a, old[i]);
