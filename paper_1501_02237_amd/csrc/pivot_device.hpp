@@ -296,25 +296,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
         for (int t = 0; t < K; t++) sum += x[t];
         const int64_t c0 = (int64_t)D - sum;
         // facets: opposite the point pivoted at step t (row t), then opposite
-        // v0; lane t keeps the neighbour across facet t and the point entering
-        uint64_t mine = 0;
-        int my_u = 0;
+        // v0; lane t keeps the point entering across facet t (-1: none, the
+        // facet is on the boundary of the hull) and the point leaving.  The
+        // heights of the points beyond a facet are >= 0 (a point below has
+        // ended the cell above), so each lane's ratio numerator is rounded
+        // to float once for all facets.
+        const float fS = ratio_num((uint64_t)(S > 0 ? S : 0));
+        int my_u = -1, my_v = 0;
 #pragma unroll
         for (int t = 0; t <= K; t++) {
-          const int64_t c = t < K ? (int64_t)x[t] : c0;
-          const int64_t cs = neg ? -c : c; // lambda * |D|
-          const bool beyond = other && cs < 0;
-          const RatioMin rm = ratio_min(beyond ? S : 0, beyond ? (int32_t)(-cs) : 0);
-          const int u = rm.lane;
+          int32_t den; // lambda * |D| negated, for the points beyond the facet
+          if (t < K) {
+            const int32_t cs = neg ? -x[t] : x[t];
+            den = other && cs < 0 ? -cs : 0;
+          } else {
+            const int64_t cs = neg ? -c0 : c0;
+            den = other && cs < 0 ? (int32_t)(-cs) : 0;
+          }
+          const RatioMin rm = ratio_min_nonneg(fS, S, den);
           if ((rm.lanes & (rm.lanes - 1)) && lane == 0) atomicOr(&a.cnt->flags, PIVOT_TIE); // equal minima
-          if (u >= 0) { // (none: the facet is on the boundary of the hull)
-            const int v = t < K ? pivlane[t] : v0;
-            if (lane == t) {
-              mine = (Cc & ~(1ull << v)) | (1ull << u);
-              my_u = u;
-            }
+          if (lane == t) {
+            my_u = rm.lane;
+            my_v = t < K ? pivlane[t] : v0;
           }
         }
+        const uint64_t mine = my_u >= 0 ? (Cc & ~(1ull << my_v)) | (1ull << my_u) : 0ull;
         // lane t inserts the neighbour across facet t: all probes in one round
         const bool fresh = mine && set_insert(a, mine);
         // The level's room: `committed` holds the insertions made plus k + 1

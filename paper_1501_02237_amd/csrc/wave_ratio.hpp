@@ -49,10 +49,9 @@ struct RatioMin {
 
 // Exact minimum of num / den over the lanes with den > 0 (den <= 0: no
 // candidate).  Every lane must be active.
-__device__ __forceinline__ RatioMin ratio_min(int64_t num, int32_t den) {
+// The minimum over the lanes with a candidate (has), given each lane's key.
+__device__ __forceinline__ RatioMin ratio_min_keyed(uint32_t key, bool has, int64_t num, int32_t den) {
   constexpr uint32_t BAND = 64;
-  const bool has = den > 0;
-  const uint32_t key = has ? ratio_key(num, has ? den : 1) : 0xFFFFFFFFu;
   const uint32_t kmin = wave_umin(key);
   RatioMin r;
   r.lane = -1;
@@ -87,6 +86,24 @@ __device__ __forceinline__ RatioMin ratio_min(int64_t num, int32_t den) {
     }
   }
   return r;
+}
+
+__device__ __forceinline__ RatioMin ratio_min(int64_t num, int32_t den) {
+  const bool has = den > 0;
+  return ratio_min_keyed(has ? ratio_key(num, has ? den : 1) : 0xFFFFFFFFu, has, num, den);
+}
+
+// float |num| as ratio_key rounds it, for a numerator shared by many minima
+__device__ __forceinline__ float ratio_num(uint64_t mag) {
+  return __builtin_fmaf((float)(uint32_t)(mag >> 32), 4294967296.0f, (float)(uint32_t)mag);
+}
+
+// ratio_min for num >= 0 with fnum = ratio_num(num) computed once by the
+// caller: the same keys, bit for bit (a ratio >= 0 has its sign bit clear).
+__device__ __forceinline__ RatioMin ratio_min_nonneg(float fnum, int64_t num, int32_t den) {
+  const bool has = den > 0;
+  const float r = fnum * __builtin_amdgcn_rcpf((float)(has ? den : 1));
+  return ratio_min_keyed(has ? (__float_as_uint(r) | 0x80000000u) : 0xFFFFFFFFu, has, num, den);
 }
 
 } // namespace dev
